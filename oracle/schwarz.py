@@ -1,0 +1,286 @@
+"""Overlapping Schwarz smoothers of Sec. 3.1 (oracle; test infrastructure).
+
+Subdomains (per direction d, in the 1D global index I = m (P+1) + i):
+* element-centred (EC) for element m: the element's P+1 nodes plus N_O node
+  layers of each neighbour: I in [m(P+1) - N_O, (m+1)(P+1) + N_O);
+* face-centred (FC) normal to d, for the face f between elements f-1 and f:
+  the two adjoining elements without their far nodes: I in
+  [(f-1)(P+1) + 1, f(P+1) + P), i.e. 2P nodes; laterally the EC range.
+Nodes outside the domain are dropped (Dirichlet) or wrapped (periodic).
+
+Local problems: A_ss = R_s A R_s^T, solved either densely (Cholesky of the
+restricted matrix: the definition) or by fast diagonalisation with the 1D
+generalised eigenpairs L_{s,d} S = M_{s,d} S Lambda (Sec. 3.1).
+
+Weights (eq. (weight function:ec), eq. (weight function:fc)):
+  w_H(xi_H) = 1/2 [phi((1 + xi_H)/dxi_O) + phi((1 - xi_H)/dxi_O)],
+  dxi_O = eta_{N_O} + 1, xi_H = xi in the core element, xi -/+ 2 in its
+  left/right neighbour; phi = the smoothed sign function (quintic, cubic),
+  phi = 1 (unweighted) or phi~ = 0 (arithmetic averaging).
+Readings: N_O = 0 gives weight 1 on the core; on a Dirichlet side the missing
+term is replaced by 1; the face-centred normal weight is read as
+  w_F(xi_F) = 1/2 [1 + phi(1 - |xi_F|)]
+(1 at the face, 1/2 at the element mid-plane, 0 at the excluded far node), the
+form for which the face patches of one orientation sum to one: the printed
+phi(|xi_F|) does not.
+
+Sweeps: EA = one additive sweep over all EC patches; FA = one additive sweep
+per orientation d = 1..D in sequence, the residual recomputed before each.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Tuple
+
+import numpy as np
+import scipy.linalg as sla
+
+from .gll import gll
+
+
+# --------------------------------------------------------------------------- weights
+
+def phi_tilde(x, kind: str):
+    """Smoothed sign functions: cubic (3x - x^3)/2, quintic (15x - 10x^3 + 3x^5)/8."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == "cubic":
+        return (3.0 * x - x ** 3) / 2.0
+    if kind == "quintic":
+        return (15.0 * x - 10.0 * x ** 3 + 3.0 * x ** 5) / 8.0
+    if kind == "arith":
+        return np.zeros_like(x)
+    raise ValueError(kind)
+
+
+def phi(x, kind: str):
+    """phi(x) = phi~(x) inside (-1, 1), sgn(x) outside; phi = 1 when unweighted."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == "none":
+        return np.ones_like(x)
+    inside = np.abs(x) < 1.0
+    return np.where(inside, phi_tilde(np.clip(x, -1.0, 1.0), kind), np.sign(x))
+
+
+def w_hat(xi_h, dxi_o, kind, left_boundary=False, right_boundary=False):
+    """Hat-shaped EC / lateral weight w_H (eq. (weight function:ec))."""
+    a = np.ones_like(np.asarray(xi_h, dtype=np.float64)) if left_boundary else phi((1.0 + xi_h) / dxi_o, kind)
+    b = np.ones_like(np.asarray(xi_h, dtype=np.float64)) if right_boundary else phi((1.0 - xi_h) / dxi_o, kind)
+    return 0.5 * (a + b)
+
+
+def w_face(xi_f, kind):
+    """Face-centred normal weight w_F (eq. (weight function:fc), read as phi(1 - |xi_F|))."""
+    return 0.5 * (1.0 + phi(1.0 - np.abs(xi_f), kind))
+
+
+# --------------------------------------------------------------------------- 1D patch sets
+
+@dataclass
+class Patch1D:
+    idx: np.ndarray        # global 1D indices (patch-local order)
+    w: np.ndarray          # 1D weights on those indices
+
+
+def ec_patches_1d(P: int, N: int, periodic: bool, n_o: int, kind: str) -> List[Patch1D]:
+    eta, _ = gll(P)
+    NP = P + 1
+    out = []
+    for m in range(N):
+        g = np.arange(m * NP - n_o, (m + 1) * NP + n_o)
+        if periodic:
+            keep = np.ones(len(g), bool)
+            gw = g % (N * NP)
+        else:
+            keep = (g >= 0) & (g < N * NP)
+            gw = g
+        g_raw = g[keep]
+        idx = gw[keep]
+        mm = np.floor_divide(g_raw, NP)          # element index before wrapping
+        i = g_raw - mm * NP
+        xi_h = eta[i] + 2.0 * (mm - m)
+        if n_o == 0:
+            w = np.ones(len(idx))
+        else:
+            dxi_o = eta[n_o] + 1.0
+            lb = (not periodic) and m == 0
+            rb = (not periodic) and m == N - 1
+            w = w_hat(xi_h, dxi_o, kind, lb, rb)
+        out.append(Patch1D(idx.astype(np.int64), w))
+    return out
+
+
+def fc_patches_1d(P: int, N: int, periodic: bool, kind: str) -> List[Patch1D]:
+    eta, _ = gll(P)
+    NP = P + 1
+    out = []
+    nf = N if periodic else N + 1
+    for f in range(nf):
+        g = np.arange((f - 1) * NP + 1, f * NP + P)
+        if periodic:
+            keep = np.ones(len(g), bool)
+            gw = g % (N * NP)
+        else:
+            keep = (g >= 0) & (g < N * NP)
+            gw = g
+        g_raw = g[keep]
+        idx = gw[keep]
+        mm = np.floor_divide(g_raw, NP)
+        i = g_raw - mm * NP
+        xi = eta[i]
+        xi_f = np.where(mm == f - 1, xi - 1.0, xi + 1.0)
+        w = w_face(xi_f, kind)
+        out.append(Patch1D(idx.astype(np.int64), w))
+    return out
+
+
+# --------------------------------------------------------------------------- level context
+
+def overlap_for(P_l: int, overlap) -> int:
+    """N_O on level l.
+
+    'level': 1 + P_l/8 rounded to the nearest integer, halves up (Sec. 4.3
+    prints a floor; with the floor N_O = 1 for P_l <= 4, where every weighting
+    gives the same weights, yet Table 2 lists different rates for cubic and
+    quintic weighting at P = 4; rounding reproduces Tables 2 and 3 and agrees
+    with the floor for P_l >= 8).  'level_floor': 1 + floor(P_l/8) as printed.
+    'zero': 0.  An int: that value on every level.
+    """
+    if overlap == "level":
+        return 1 + (2 * P_l + 8) // 16
+    if overlap == "level_floor":
+        return 1 + P_l // 8
+    if overlap == "zero":
+        return 0
+    return int(overlap)
+
+
+@dataclass
+class SmootherLevel:
+    grid: object
+    P: int
+    n_o: int
+    kind: str
+    smoother: str            # "EA" or "FA"
+    apply_A: object          # callable u_lex -> A u_lex
+    A: object                # sparse matrix (lex) or None
+    ops: list                # per direction (Mvec, Ldense)
+    mode: str = "fdm"        # "fdm" or "dense"
+    ec: list = field(default_factory=list)     # per direction list[Patch1D]
+    fc: list = field(default_factory=list)
+    _eig: Dict = field(default_factory=dict)
+    _chol: Dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        g = self.grid
+        for d in range(g.dim):
+            self.ec.append(ec_patches_1d(self.P, g.n[d], g.periodic[d], self.n_o, self.kind))
+            self.fc.append(fc_patches_1d(self.P, g.n[d], g.periodic[d], self.kind))
+
+    @property
+    def shape(self):
+        return tuple(nd * (self.P + 1) for nd in reversed(self.grid.n))
+
+    # ---- 1D generalised eigenpairs  L_{s,d} S = M_{s,d} S Lambda
+    def eig1d(self, d: int, kind: str, k: int):
+        key = (d, kind, k)
+        if key not in self._eig:
+            p = (self.fc if kind == "fc" else self.ec)[d][k]
+            Mv, L = self.ops[d]
+            Ls = L[np.ix_(p.idx, p.idx)]
+            Ms = np.diag(Mv[p.idx])
+            lam, S = sla.eigh(0.5 * (Ls + Ls.T), Ms)
+            self._eig[key] = (S, lam)
+        return self._eig[key]
+
+    def patch_sets(self, normal: int):
+        """List of tuples (per-direction (kind, k)) of the partition used in one sweep."""
+        dim = self.grid.dim
+        choices = []
+        for d in range(dim):
+            if d == normal:
+                choices.append([("fc", k) for k in range(len(self.fc[d]))])
+            else:
+                choices.append([("ec", k) for k in range(len(self.ec[d]))])
+        out = []
+        for combo in np.ndindex(*[len(c) for c in choices]):
+            out.append(tuple(choices[d][combo[d]] for d in range(dim)))
+        return out
+
+    def patch_1d(self, d, kk):
+        kind, k = kk
+        return (self.fc if kind == "fc" else self.ec)[d][k]
+
+    def solve_patch(self, sig, r_patch: np.ndarray, glob_idx: np.ndarray) -> np.ndarray:
+        """Delta u_s = A_ss^{-1} r_s on the tensor patch (array axes: slowest direction first)."""
+        dim = self.grid.dim
+        if self.mode == "dense":
+            key = sig
+            if key not in self._chol:
+                Ass = self.A[glob_idx][:, glob_idx].toarray()
+                self._chol[key] = sla.cho_factor(Ass)
+            return sla.cho_solve(self._chol[key], r_patch.reshape(-1)).reshape(r_patch.shape)
+        # fast diagonalisation: (x)S (sum Lambda)^-1 (x)S^T
+        Ss, lams = [], []
+        for d in range(dim):
+            S, lam = self.eig1d(d, sig[d][0], sig[d][1])
+            Ss.append(S)
+            lams.append(lam)
+        t = r_patch
+        for d in range(dim):
+            ax = dim - 1 - d
+            t = np.moveaxis(np.tensordot(Ss[d].T, np.moveaxis(t, ax, 0), axes=(1, 0)), 0, ax)
+        denom = np.zeros(t.shape)
+        for d in range(dim):
+            ax = dim - 1 - d
+            sh = [1] * dim
+            sh[ax] = -1
+            denom = denom + lams[d].reshape(sh)
+        t = t / denom
+        for d in range(dim):
+            ax = dim - 1 - d
+            t = np.moveaxis(np.tensordot(Ss[d], np.moveaxis(t, ax, 0), axes=(1, 0)), 0, ax)
+        return t
+
+    def sweep(self, u: np.ndarray, f: np.ndarray, normal: int) -> np.ndarray:
+        """One additive sweep over a partition: u + sum_s R_s^T (w_s Delta u_s)."""
+        dim = self.grid.dim
+        shape = self.shape
+        r = (f - self.apply_A(u)).reshape(shape)
+        corr = np.zeros(shape)
+        strides = [1]
+        for d in range(dim - 1):
+            strides.append(strides[-1] * shape[dim - 1 - d])
+        for sig in self.patch_sets(normal):
+            p1 = [self.patch_1d(d, sig[d]) for d in range(dim)]
+            ix = np.ix_(*[p1[d].idx for d in reversed(range(dim))])
+            rs = r[ix]
+            gidx = None
+            if self.mode == "dense":
+                gidx = np.zeros([len(p1[d].idx) for d in reversed(range(dim))], dtype=np.int64)
+                for d in range(dim):
+                    ax = dim - 1 - d
+                    sh = [1] * dim
+                    sh[ax] = -1
+                    gidx = gidx + (p1[d].idx * strides[d]).reshape(sh)
+                gidx = gidx.reshape(-1)
+            du = self.solve_patch(sig, rs, gidx)
+            w = np.ones(du.shape)
+            for d in range(dim):
+                ax = dim - 1 - d
+                sh = [1] * dim
+                sh[ax] = -1
+                w = w * p1[d].w.reshape(sh)
+            corr[ix] += w * du          # indices are distinct within one patch
+        return u + corr.reshape(-1)
+
+    def smooth(self, u: np.ndarray, f: np.ndarray, steps: int) -> np.ndarray:
+        """`steps` Schwarz iterations (EA: one sweep each; FA: one sweep per direction)."""
+        for _ in range(steps):
+            if self.smoother == "EA":
+                u = self.sweep(u, f, normal=-1)
+            elif self.smoother == "FA":
+                for d in range(self.grid.dim):
+                    u = self.sweep(u, f, normal=d)
+            else:
+                raise ValueError(self.smoother)
+        return u

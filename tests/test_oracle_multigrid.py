@@ -1,0 +1,128 @@
+"""Pins of the oracle's multigrid and MGCG: transfers, exact coarse solve, and the
+paper's printed convergence rates (Tables 2-4, golden fixture)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import metrics as me
+from oracle import multigrid as mg
+from oracle import operator as op
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+
+
+def test_level_orders():
+    assert mg.level_orders(8) == [1, 2, 4, 8]
+    assert mg.level_orders(32) == [1, 2, 4, 8, 16, 32]
+    assert mg.level_orders(12) == [1, 3, 6, 12]
+    assert mg.level_orders(6) == [1, 3, 6]
+    assert mg.level_orders(1) == [1]
+
+
+def test_transfers_exact_and_adjoint():
+    g = synth.uniform_grid(3, 2, 1.0, False)
+    m = synth.Method(P=4, smoother="FA")
+    h = mg.Hierarchy(g, m)
+    # prolongation reproduces a coarse polynomial (degree <= 2 per direction)
+    xs2 = [op.node_coords_1d(np.asarray(g.dx[d]), 2) for d in range(3)]
+    xs4 = [op.node_coords_1d(np.asarray(g.dx[d]), 4) for d in range(3)]
+    def poly(xs):
+        Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        return (X ** 2 - 0.3 * Y * Z + Z ** 2 * X).reshape(-1)
+    assert np.allclose(h.prolong(2, poly(xs2)), poly(xs4), atol=1e-12)
+    rng = np.random.default_rng(0)
+    uc = rng.standard_normal(len(poly(xs2)))
+    vf = rng.standard_normal(len(poly(xs4)))
+    assert h.prolong(2, uc) @ vf == pytest.approx(uc @ h.restrict(2, vf), rel=1e-12)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_coarse_solve_exact(periodic):
+    g = synth.uniform_grid(2, 4, 1.0, periodic)
+    h = mg.Hierarchy(g, synth.Method(P=2))
+    A0 = h.levels[0].A
+    f = np.random.default_rng(1).standard_normal(A0.shape[0])
+    if periodic:
+        f -= f.mean()
+    x = h.coarse_solve(f)
+    assert np.allclose(A0 @ x, f, atol=1e-11 * np.abs(f).max())
+    if periodic:
+        assert abs(x.mean()) < 1e-13
+
+
+@pytest.mark.parametrize("smoother", ["EA", "FA"])
+def test_mgcg_reaches_tolerance_3d_dirichlet(smoother):
+    rng = np.random.default_rng(5)
+    g = synth.Grid(3, tuple(rng.uniform(0.5, 1.5, 3) for _ in range(3)), (False,) * 3)
+    m = synth.Method(P=4, smoother=smoother, flux="ldg", beta=(0.5, 0.5, 0.5))
+    h = mg.Hierarchy(g, m)
+    f = rng.uniform(-1, 1, h.levels[-1].A.shape[0])
+    res = mg.mgcg(h, f, np.zeros_like(f), tol=1e-10)
+    assert res.converged and res.iterations < 20
+    r_true = np.linalg.norm(f - h.levels[-1].A @ res.x)
+    assert r_true <= 1.5e-10 * np.linalg.norm(f)
+
+
+def _paper_run(row, seed=1):
+    w = synth.paper_periodic_2d(row["P"], n=row["n"], ar=row["ar"], smoother=row["smoother"],
+                                overlap=row["overlap"], beta=row["beta"], krylov=row["krylov"],
+                                weighting=row["weighting"], vcycle=row["vcycle"])
+    g, m = w.grid, w.method
+    h = mg.Hierarchy(g, m, patch_mode="fdm")
+    P = m.P
+    xs = [op.node_coords_1d(np.asarray(g.dx[d]), P) for d in range(2)]
+    X, Y = np.meshgrid(xs[0], xs[1])
+    f = (2 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(np.pi * Y)).reshape(-1)
+    gvec = op.mass_vector(g, P) * f
+    gvec -= gvec.mean()
+    u0 = np.random.default_rng(seed).uniform(0, 1, size=len(gvec))
+    solver = mg.mgcg if m.krylov else mg.mg_solve
+    return solver(h, gvec, u0, tol=1e-10, i_max=400)
+
+
+def _rows():
+    with open(GOLD) as fh:
+        return json.load(fh)["rows"]
+
+
+@pytest.mark.parametrize("row", _rows(), ids=lambda r: r["cite"][:60])
+def test_paper_convergence_rates(row):
+    """r_bar within 12 % (FA_l rows run about 5 % below the printed values) and
+    n10 within one cycle of the printed tables."""
+    res = _paper_run(row)
+    n10 = me.n10(res.history)
+    assert n10 is not None
+    rb = me.r_bar(res.history, n10)
+    tol = 0.12 if (row["smoother"] == "FA" and row["overlap"] == "level") else 0.06
+    assert rb == pytest.approx(row["r_bar"], rel=tol), (rb, row["r_bar"])
+    if row["n10"] is not None:
+        assert abs(n10 - row["n10"]) <= 1
+
+
+def test_printed_overlap_rule_misses_table_rows():
+    """The printed N_O = 1 + floor(P_l/8) (N_O = 1 at P = 4) gives an EA_l rate far
+    below Table 3; the rounded rule used by default reproduces it."""
+    row = dict(_rows()[0])
+    row["overlap"] = "level_floor"
+    res = _paper_run(row)
+    rb = me.r_bar(res.history, me.n10(res.history))
+    assert rb < 0.8 * row["r_bar"]
+
+
+def test_cost_model_reproduces_table3_omega():
+    with open(GOLD) as fh:
+        gold = json.load(fh)
+    for key, rows in gold["omega_rows"].items():
+        if key.startswith("_"):
+            continue
+        kind = "EC" if key.startswith("E") else "FC"
+        for P, rb, om in rows:
+            n_o = 0 if key.endswith("_0") else 1 + P // 8
+            if key == "EM_0":
+                n_o = 0
+            assert me.omega_bar(rb, kind, n_o, P + 1) == pytest.approx(om, abs=0.06), (key, P)
+    w = gold["w10"]
+    assert me.w10(w["r_bar"], "EC", 3, 17) == pytest.approx(w["value"], abs=1.0)
