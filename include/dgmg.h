@@ -1,0 +1,217 @@
+/*
+ * dgmg.h - C ABI of the MI355X (gfx950) p-multigrid Poisson solver for nodal
+ * discontinuous Galerkin discretisations on Cartesian grids.
+ *
+ * Method: Stiller, "Robust multigrid for high-order discontinuous Galerkin
+ * methods: a fast Poisson solver suitable for high-aspect ratio Cartesian
+ * grids" (arXiv:1603.02524).  The library solves A u = g, the unified IP/LDG
+ * nodal DG system of eq. (discrete problem), with the inexact
+ * multigrid-preconditioned conjugate gradient method (Alg. 2), a polynomial
+ * multigrid V-cycle (Alg. 1) and overlapping additive Schwarz smoothers with
+ * element-centred (EA) or face-centred (FA) subdomains solved by fast
+ * diagonalisation (Sec. 3.1).  3D and non-periodic (homogeneous Dirichlet)
+ * grids extend the paper's 2D periodic setting.
+ *
+ * Conventions for every entry point below
+ * ---------------------------------------
+ * Vector layout: element-major GLL order.  For level l with order P_l and
+ *   N_P = P_l + 1 nodes per direction, entry
+ *     e * N_P^D + (k * N_P + j) * N_P + i,   e = m1 + N1 * (m2 + N2 * m3)
+ *   holds the coefficient u_{ijk} of element (m1, m2, m3) (all 0-based,
+ *   direction 1 fastest; in 2D k and m3 are absent).
+ * Memory: every vector argument is a caller-owned DEVICE pointer (e.g. the
+ *   data pointer of a torch tensor on the GPU) unless stated otherwise; the
+ *   library never frees caller memory.  The handle owns its host tables; all
+ *   device scratch and tables live in one workspace the caller allocates and
+ *   binds (dgmg_workspace_bytes / dgmg_bind_workspace).
+ * Streams: work is enqueued asynchronously on the handle's stream (a
+ *   hipStream_t passed as void*; NULL = default stream) unless stated
+ *   otherwise.  A handle must not be used from two host threads at once.
+ * dtype: DGMG_F64 (double) or DGMG_F32 (float) selects the element type of
+ *   the vector arguments of level operations; tables exist in both precisions.
+ * Errors: 0 on success; > 0 non-fatal status (DGMG_NOT_CONVERGED); < 0 error
+ *   (DGMG_EINVAL bad argument, DGMG_EHIP runtime failure, DGMG_ENOMEM
+ *   workspace missing or too small, DGMG_EUNSUPPORTED configuration not
+ *   built, DGMG_ENONFINITE NaN/Inf met).  dgmg_last_error() returns the
+ *   message of the most recent failure on that handle.  No exception or
+ *   signal crosses the ABI.
+ */
+#ifndef DGMG_H
+#define DGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGMG_OK 0
+#define DGMG_NOT_CONVERGED 1
+#define DGMG_EINVAL (-1)
+#define DGMG_EHIP (-2)
+#define DGMG_ENOMEM (-3)
+#define DGMG_EUNSUPPORTED (-4)
+#define DGMG_ENONFINITE (-5)
+
+#define DGMG_F64 0
+#define DGMG_F32 1
+
+#define DGMG_FLUX_IP 0  /* interior penalty fluxes (Sec. 2.3) */
+#define DGMG_FLUX_LDG 1 /* local DG fluxes with parameter beta (Sec. 2.3) */
+
+#define DGMG_SMOOTHER_EA 0 /* element-centred weighted additive Schwarz */
+#define DGMG_SMOOTHER_FA 1 /* face-centred weighted additive Schwarz */
+
+#define DGMG_OVERLAP_LEVEL (-1)       /* N_O = 1 + round(P_l / 8) on each level */
+#define DGMG_OVERLAP_LEVEL_FLOOR (-2) /* N_O = 1 + floor(P_l / 8) as printed */
+/* N_O >= 0: the same overlap on every level (0 = the paper's "0" variants) */
+
+#define DGMG_WEIGHT_QUINTIC 0
+#define DGMG_WEIGHT_CUBIC 1
+#define DGMG_WEIGHT_ARITH 2 /* arithmetic averaging (phi~ = 0) */
+#define DGMG_WEIGHT_NONE 3  /* conventional additive Schwarz (phi = 1) */
+
+#define DGMG_VCYCLE_CLASSICAL 0 /* (N_S1, N_S2) on every level */
+#define DGMG_VCYCLE_VARIABLE 1  /* counts doubled on each coarser level */
+
+#define DGMG_PREC_FP64 0  /* everything in double precision */
+#define DGMG_PREC_MIXED 1 /* V-cycle in float (coarse solve in double) inside FP64 PCG */
+
+typedef struct dgmg_handle dgmg_handle;
+
+/* Cartesian grid (Sec. 2.2).  dx[d] points to n_elem[d] HOST doubles > 0. */
+typedef struct {
+  int dim;              /* 2 or 3 */
+  int n_elem[3];        /* elements per direction (>= 1; >= 3 if periodic) */
+  const double* dx[3];  /* element sizes Delta x_d^m per direction */
+  int periodic[3];      /* 0: homogeneous Dirichlet, 1: periodic */
+} dgmg_grid;
+
+typedef struct {
+  int P;             /* top-level order, 1 <= P <= 16 */
+  int flux;          /* DGMG_FLUX_IP or DGMG_FLUX_LDG */
+  double beta[3];    /* LDG parameter per direction (Sec. 2.3); ignored for IP */
+  double mu_star;    /* penalty factor mu_star > 0 of mu = mu_0 (1 + mu_star) */
+  int smoother;      /* DGMG_SMOOTHER_* */
+  int overlap;       /* DGMG_OVERLAP_LEVEL, DGMG_OVERLAP_LEVEL_FLOOR or N_O >= 0 */
+  int weighting;     /* DGMG_WEIGHT_* */
+  int vcycle;        /* DGMG_VCYCLE_* */
+  int ns_pre;        /* pre-smoothing steps N_S1 (>= 0) */
+  int ns_post;       /* post-smoothing steps N_S2 (>= 0) */
+  int precision;     /* DGMG_PREC_* */
+  int max_iter;      /* i_max of Alg. 2 */
+} dgmg_opts;
+
+/* Statistics of one dgmg_solve call (host struct, filled on return). */
+typedef struct {
+  int iterations;          /* PCG iterations performed */
+  int converged;           /* 1 if ||r|| <= tol ||r_0|| */
+  double r0;               /* ||g - A x_0||_2 */
+  double r_final;          /* ||r|| of the recursively updated residual at exit */
+  double rho;              /* (r_final / r0)^(1/iterations), eq. (rho) */
+  double history[256];     /* ||r_i||, i = 0..min(iterations, 255) */
+} dgmg_stats;
+
+/* Fill *o with the defaults: IP, beta = 0, mu_star = 1, FA, level overlap,
+ * quintic weights, classical V(1,1), FP64, max_iter = 100.  P is set to 4. */
+int dgmg_opts_default(dgmg_opts* o);
+
+/* Host-side setup (Sec. 2.4, Sec. 3.1, Sec. 3.2): builds the level series
+ * P_L = P, P_{l-1} = floor(P_l / 2), ..., 1; per level the 1D DG operators of
+ * eq. (L:generic) with their face penalties; per subdomain and direction the
+ * generalised eigenpairs of (L_{s,d}, M_{s,d}) and the 1D weights; the
+ * embedded interpolation; and the global 1D eigenpairs used for the exact
+ * coarse solve.  All in double precision on the host.  No device memory is
+ * touched.  On success *out owns a new handle (free with dgmg_destroy).
+ * Errors: DGMG_EINVAL for dim not in {2,3}, P out of range, n_elem < 1,
+ * dx <= 0 or not finite, mu_star <= 0, |beta| > 1, periodic with n_elem < 3,
+ * bad enum values; DGMG_EUNSUPPORTED for (P, N_O) pairs without kernels. */
+int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out);
+
+/* Bytes of device workspace the handle needs (tables, level vectors, patch
+ * buffers, PCG vectors, reduction scratch).  *bytes is a host size_t. */
+int dgmg_workspace_bytes(const dgmg_handle* h, size_t* bytes);
+
+/* Bind caller-allocated device memory of at least dgmg_workspace_bytes bytes
+ * (256-byte aligned) and upload the tables on `stream` (synchronised before
+ * return).  The memory must stay valid until dgmg_destroy or the next bind. */
+int dgmg_bind_workspace(dgmg_handle* h, void* dev, size_t bytes, void* stream);
+
+/* Change the stream later work is enqueued on. */
+int dgmg_set_stream(dgmg_handle* h, void* stream);
+
+/* Number of levels L + 1 and, per level l (0 = coarsest), its order P_l,
+ * overlap N_O,l and number of unknowns (host outputs; NULL allowed). */
+int dgmg_num_levels(const dgmg_handle* h);
+int dgmg_level_info(const dgmg_handle* h, int level, int* P, int* n_o, int64_t* n_dof);
+
+/* Host copy of the 1D node coordinates of level `level` in direction d
+ * (n_elem[d] * (P_l + 1) doubles, element by element; element map of
+ * Sec. 2.2 with the grid starting at 0). */
+int dgmg_node_coords(const dgmg_handle* h, int level, int d, double* x_host);
+
+/* y = A_l x (eq. (discrete problem); sum factorised).  x, y: device vectors
+ * of level l, distinct. */
+int dgmg_apply(dgmg_handle* h, int level, const void* x, void* y, int dtype);
+
+/* r = f - A_l x (residual form of Sec. 3.1).  r must not alias x. */
+int dgmg_residual(dgmg_handle* h, int level, const void* f, const void* x, void* r, int dtype);
+
+/* nsteps Schwarz iterations on level l >= 1 (Smoother of Alg. 1): EA = one
+ * additive sweep over all element-centred subdomains per step; FA = one sweep
+ * per orientation d = 1..D in sequence, the residual recomputed before each
+ * (eq. (correction:global), eq. (weight function:ec), eq. (weight
+ * function:fc)).  u is updated in place; f unchanged. */
+int dgmg_smooth(dgmg_handle* h, int level, void* u, const void* f, int nsteps, int dtype);
+
+/* f_{l-1} = I_l^T r_l: restriction by the transpose of the embedded
+ * interpolation (Sec. 3.2).  level >= 1. */
+int dgmg_restrict(dgmg_handle* h, int level, const void* r_fine, void* f_coarse, int dtype);
+
+/* u_l += I_l u_{l-1}: prolongation by embedded interpolation.  level >= 1. */
+int dgmg_prolong(dgmg_handle* h, int level, const void* u_coarse, void* u_fine, int dtype);
+
+/* u_0 = A_0^+ f_0 on the coarsest level (P = 1), line of Alg. 1: computed
+ * exactly by global fast diagonalisation of the Kronecker-sum operator, in
+ * double precision (float vectors are converted).  For periodic grids f_0 is
+ * made orthogonal to the constants and the mean-free solution is returned. */
+int dgmg_coarse_solve(dgmg_handle* h, const void* f0, void* u0, int dtype);
+
+/* z = MultigridCycle(0, r) (Alg. 1) on the top level.  In mixed precision the
+ * V-cycle runs in float; r and z are then float vectors (dtype DGMG_F32). */
+int dgmg_vcycle(dgmg_handle* h, const void* r, void* z, int dtype);
+
+/* Solve A x = rhs by MGCG (Alg. 2, with beta = z^T (r - r_old) / delta) until
+ * ||r||_2 <= tol ||rhs - A x_0||_2 or max_iter iterations.  rhs, x: FP64
+ * device vectors of the top level; x holds the initial guess on entry and the
+ * iterate on exit.  Synchronises the stream once per iteration (exit test).
+ * st (host, may be NULL) receives iteration count and residual history.
+ * Returns DGMG_OK, DGMG_NOT_CONVERGED or an error (DGMG_ENONFINITE when a
+ * residual norm is NaN/Inf). */
+int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_stats* st);
+
+/* g = M f: the GLL load vector of Sec. 2.4 from nodal values f (FP64 device
+ * vectors of the top level). */
+int dgmg_mass(dgmg_handle* h, const double* f_nodal, double* g);
+
+/* Per-kernel timing with HIP events on the handle's stream.  enable != 0
+ * starts recording the Schwarz patch-solve kernel launches (and clears the
+ * totals); dgmg_kernel_time reads, after synchronisation, the summed
+ * milliseconds, launch count and algorithmic flops and bytes of those
+ * launches (host outputs; NULL allowed). */
+int dgmg_kernel_timing(dgmg_handle* h, int enable);
+int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double* flops,
+                     double* bytes);
+
+/* Release host tables and HIP objects of the handle (not the workspace). */
+void dgmg_destroy(dgmg_handle* h);
+
+/* Message of the last failure on h (or of the last failed dgmg_setup when h
+ * is NULL).  The string is owned by the library. */
+const char* dgmg_last_error(const dgmg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGMG_H */

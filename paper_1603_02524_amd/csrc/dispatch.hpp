@@ -1,0 +1,77 @@
+// Runtime -> template dispatch for the kernels of kernels.hpp.  Included by one
+// translation unit per (precision, dimension) so they compile in parallel.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace dgmg {
+
+// Orders with kernels: P in {1, 2, 3, 4, 6, 8, 12, 16}  (NP = P + 1).
+#define DGMG_NP_LIST(X) X(2) X(3) X(4) X(5) X(7) X(9) X(13) X(17)
+// Transfer pairs (NP fine, NP coarse) for P -> floor(P / 2).
+#define DGMG_XFER_LIST(X) X(3, 2) X(4, 2) X(5, 3) X(7, 4) X(9, 5) X(13, 7) X(17, 9)
+// Patch tiles (NA, NL): element-centred (n, n) with n = NP + 2 N_O and
+// face-centred (2P, NP + 2 N_O) for the overlaps N_O the level rules produce
+// (and N_O = 0, 1 for the zero-overlap variants).
+#define DGMG_FDM_LIST(X)                                                                    \
+  X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 7) X(9, 9) X(11, 11) X(13, 13) X(15, 15) X(17, 17) \
+  X(19, 19) X(21, 21) X(23, 23) X(4, 3) X(4, 5) X(6, 4) X(8, 5) X(8, 7) X(8, 9) X(12, 7)  \
+  X(12, 9) X(12, 11) X(16, 9) X(16, 11) X(16, 13) X(16, 15) X(24, 13) X(24, 17) X(24, 19) \
+  X(32, 17) X(32, 21) X(32, 23)
+
+template <class T, int DIM>
+int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
+                        int* nblk, hipStream_t s) {
+  switch (L.NP) {
+#define DGMG_CASE(NP) \
+  case NP: return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
+#define DGMG_CASE(A, B) \
+  if (NA == A && NL == B) return true;
+  DGMG_FDM_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return false;
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx,
+                      int npy, int npz, hipStream_t s) {
+#define DGMG_CASE(A, B) \
+  if (NA == A && NL == B) return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, s);
+  DGMG_FDM_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return -4;
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
+                          int npy, int npz, hipStream_t s) {
+  switch (L.NP) {
+#define DGMG_CASE(NP) \
+  case NP: return combine_launch_t<T, DIM, NP>(L, nd, NA, NL, buf, u, npx, npy, npz, s);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out,
+                           hipStream_t s) {
+#define DGMG_CASE(F, C)                                                                          \
+  if (Lf.NP == F && Lf.NPc == C)                                                                 \
+    return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, s)        \
+                     : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, s);
+  DGMG_XFER_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return -4;
+}
+
+}  // namespace dgmg

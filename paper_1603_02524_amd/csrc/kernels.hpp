@@ -1,0 +1,575 @@
+// HIP kernels for gfx950 (MI355X): sum-factorised DG operator, Schwarz patch
+// solves by fast diagonalisation, deterministic overlap summation, p-transfers.
+//
+// Vector layout (all kernels): element-major, element e = m1 + N1 (m2 + N2 m3),
+// local node (k NP + j) NP + i, direction 1 fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgmg {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int round64(int a) { return (a + 63) / 64 * 64; }
+
+constexpr int NUM_XCD = 8;  // MI355X: 8 accelerator complex dies, blocks dispatched round-robin
+
+// Logical block index such that each XCD receives one contiguous range of
+// logical blocks (neighbouring elements then share that XCD's L2).  The grid
+// is launched with NUM_XCD * ceil(G / NUM_XCD) blocks; returns -1 for padding.
+__device__ __forceinline__ int xcd_block(int G) {
+  const int per = (G + NUM_XCD - 1) / NUM_XCD;
+  const int b = blockIdx.x;
+  const int lb = (b % NUM_XCD) * per + b / NUM_XCD;
+  return lb < G ? lb : -1;
+}
+inline int xcd_grid(int G) { return NUM_XCD * ((G + NUM_XCD - 1) / NUM_XCD); }
+
+enum { ECOEF_N = 8, E_TWO_DX = 0, E_HALF_DX, E_CL, E_CNL, E_BL, E_CR, E_CNR, E_BR };
+
+template <class T>
+struct DirDev {
+  int N = 1, periodic = 0;
+  int n_ec = 0, n_fc = 0, nf = 0;
+  const T* ecoef = nullptr;  // N * 8 (see ECOEF enum)
+  const int* nbr = nullptr;  // N * 2
+  const T* S_ec = nullptr;   // N * n_ec^2, row-major S[k][j]
+  const T* lam_ec = nullptr;
+  const T* w_ec = nullptr;
+  const T* S_fc = nullptr;   // nf * n_fc^2
+  const T* lam_fc = nullptr;
+  const T* w_fc = nullptr;
+};
+
+template <class T>
+struct LevelDev {
+  int dim = 3, P = 1, NP = 2, NO = 0, NPc = 0;
+  int n_elem = 0;
+  int64_t n_dof = 0;
+  const T* Ls = nullptr;   // NP*NP
+  const T* D = nullptr;    // NP*NP, D[i*NP+k] = phi_k'(eta_i)
+  const T* rho = nullptr;  // NP
+  const T* J = nullptr;    // NP x NPc interpolation from the coarser level
+  DirDev<T> dir[3];
+};
+
+// ---------------------------------------------------------------- block reduction
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed shuffle tree then fixed order over waves).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  return s;  // valid in thread 0
+}
+
+// ================================================================ operator apply
+// y = A x (MODE 0), y = f - A x (MODE 1), y = A x plus per-block partial x.y (MODE 2).
+// One thread owns one line of one element per direction; neighbour traces and
+// normal derivatives are read from the neighbour's line (eq. (L:generic)).
+template <int NP, int DIM>
+constexpr int apply_epb() {
+  return imax(1, 256 / ipow(NP, DIM - 1));
+}
+template <int NP, int DIM>
+constexpr int apply_threads() {
+  return imin(1024, round64(apply_epb<NP, DIM>() * ipow(NP, DIM - 1)));
+}
+
+template <class T, int DIM, int NP, int MODE>
+__global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __restrict__ x,
+                                                     const T* __restrict__ f, T* __restrict__ y,
+                                                     double* __restrict__ part, int nblk) {
+  constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = apply_epb<NP, DIM>();
+  constexpr int P = NP - 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sx = reinterpret_cast<T*>(smem_raw);
+  T* sy = sx + EPB * NE;
+  __shared__ double red[16];
+  const int blk = xcd_block(nblk);
+  if (blk < 0) return;
+  const int e0 = blk * EPB;
+  const int ne = imin(EPB, L.n_elem - e0);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int64_t g0 = (int64_t)e0 * NE;
+  for (int q = tid; q < ne * NE; q += nth) {
+    sx[q] = x[g0 + q];
+    sy[q] = T(0);
+  }
+  __syncthreads();
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  const T* __restrict__ Ls = L.Ls;
+  const T* __restrict__ D0 = L.D;
+  const T* __restrict__ DP = L.D + P * NP;
+  const T* __restrict__ rho = L.rho;
+#pragma unroll 1
+  for (int d = 0; d < DIM; ++d) {
+    const DirDev<T> dd = L.dir[d];
+    for (int ln = tid; ln < ne * NLN; ln += nth) {
+      const int el = ln / NLN, t = ln - el * NLN;
+      const int e = e0 + el;
+      int m[3];
+      m[0] = e % N1;
+      m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
+      m[2] = DIM == 3 ? e / (N1 * N2) : 0;
+      const int estride = d == 0 ? 1 : (d == 1 ? N1 : N1 * N2);
+      // line base and stride inside the element; indices of the other directions
+      int base, stride, ia, ib;  // ia, ib: local indices of the two other directions (in order)
+      if (d == 0) {
+        base = t * NP; stride = 1; ia = t % NP; ib = t / NP;
+      } else if (d == 1) {
+        ia = t % NP; ib = t / NP; base = ia + ib * NP * NP; stride = NP;
+      } else {
+        ia = t % NP; ib = t / NP; base = t; stride = NP * NP;
+      }
+      T v[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) v[k] = sx[el * NE + base + k * stride];
+      const T* c = dd.ecoef + m[d] * ECOEF_N;
+      T d0 = 0, dP = 0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        d0 += D0[k] * v[k];
+        dP += DP[k] * v[k];
+      }
+      const int nl = dd.nbr[2 * m[d]], nr = dd.nbr[2 * m[d] + 1];
+      T uL = 0, dL = 0, uR = 0, dR = 0;
+      if (nl >= 0) {
+        const T* w = x + (int64_t)(e + (nl - m[d]) * estride) * NE + base;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const T wk = w[k * stride];
+          dL += DP[k] * wk;
+          if (k == P) uL = wk;
+        }
+      }
+      if (nr >= 0) {
+        const T* w = x + (int64_t)(e + (nr - m[d]) * estride) * NE + base;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const T wk = w[k * stride];
+          dR += D0[k] * wk;
+          if (k == 0) uR = wk;
+        }
+      }
+      const T jl = v[0] - uL, jr = v[P] - uR;
+      const T fl = c[E_CL] * d0 + c[E_CNL] * dL + c[E_BL] * jl;
+      const T fr = -c[E_CR] * dP - c[E_CNR] * dR + c[E_BR] * jr;
+      const T cl = c[E_CL] * jl, cr = c[E_CR] * jr, tdx = c[E_TWO_DX];
+      // mass factor of the other directions at this line
+      T mo;
+      if (DIM == 2) {
+        const int od = 1 - d;
+        mo = L.dir[od].ecoef[m[od] * ECOEF_N + E_HALF_DX] * rho[ia];
+      } else {
+        const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+        mo = L.dir[da].ecoef[m[da] * ECOEF_N + E_HALF_DX] * rho[ia] *
+             L.dir[db].ecoef[m[db] * ECOEF_N + E_HALF_DX] * rho[ib];
+      }
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s += Ls[i * NP + k] * v[k];
+        T o = tdx * s + cl * D0[i] - cr * DP[i];
+        if (i == 0) o += fl;
+        if (i == P) o += fr;
+        sy[el * NE + base + i * stride] += mo * o;
+      }
+    }
+    __syncthreads();
+  }
+  double acc = 0.0;
+  for (int q = tid; q < ne * NE; q += nth) {
+    const T val = sy[q];
+    if (MODE == 0) {
+      y[g0 + q] = val;
+    } else if (MODE == 1) {
+      y[g0 + q] = f[g0 + q] - val;
+    } else {
+      y[g0 + q] = val;
+      acc += (double)sx[q] * (double)val;
+    }
+  }
+  if (MODE == 2) {
+    const double s = block_sum(acc, red);
+    if (tid == 0) part[blk] = s;
+  }
+}
+
+template <class T, int DIM, int NP>
+int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
+                 int* nblk_out, hipStream_t s) {
+  constexpr int NE = ipow(NP, DIM), EPB = apply_epb<NP, DIM>(), TH = apply_threads<NP, DIM>();
+  const int nblk = (L.n_elem + EPB - 1) / EPB;
+  const size_t shm = 2 * (size_t)EPB * NE * sizeof(T);
+  if (nblk_out) *nblk_out = nblk;
+  dim3 grid(xcd_grid(nblk)), block(TH);
+  if (mode == 0) {
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 0>), grid, block, shm, s, L, x, f, y, part, nblk);
+  } else if (mode == 1) {
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 1>), grid, block, shm, s, L, x, f, y, part, nblk);
+  } else {
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 2>), grid, block, shm, s, L, x, f, y, part, nblk);
+  }
+  return 0;
+}
+
+// ================================================================ FDM patch solve
+// One patch per block.  The LDS tile is stored with the normal direction
+// fastest: tile[(l2 * NL + l1) * NA + a]; NA = 2P (face-centred normal) or the
+// element-centred size, NL = lateral size NP + 2 N_O.  Each contraction pass
+// gives every thread whole lines (kept in registers) and overwrites them in
+// place, so one tile suffices.
+template <int NA, int NL, int DIM>
+constexpr int fdm_tile() {
+  return NA * ipow(NL, DIM - 1);
+}
+template <int NA, int NL, int DIM>
+constexpr int fdm_threads() {
+  return imin(256, round64(imax(ipow(NL, DIM - 1), NA * ipow(NL, DIM - 2))));
+}
+
+template <class T, int LEN, bool FWD>
+__device__ __forceinline__ void fdm_line(T* __restrict__ tile, int base, int stride,
+                                         const T* __restrict__ S) {
+  T v[LEN];
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) v[k] = tile[base + k * stride];
+#pragma unroll
+  for (int j = 0; j < LEN; ++j) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) acc += (FWD ? S[k * LEN + j] : S[j * LEN + k]) * v[k];
+    tile[base + j * stride] = acc;
+  }
+}
+
+template <class T, int NA, int NL, int DIM, bool FWD>
+__device__ __forceinline__ void fdm_pass(T* tile, int t, const T* __restrict__ S) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (t == 0) {
+    constexpr int LINES = ipow(NL, DIM - 1);
+    for (int ln = tid; ln < LINES; ln += nth) fdm_line<T, NA, FWD>(tile, ln * NA, 1, S);
+  } else if (t == 1) {
+    constexpr int LINES = NA * ipow(NL, DIM - 2);
+    for (int ln = tid; ln < LINES; ln += nth) {
+      const int a = ln % NA, l2 = ln / NA;
+      fdm_line<T, NL, FWD>(tile, l2 * NA * NL + a, NA, S);
+    }
+  } else {
+    constexpr int LINES = NA * NL;
+    for (int ln = tid; ln < LINES; ln += nth) fdm_line<T, NL, FWD>(tile, ln, NA * NL, S);
+  }
+}
+
+template <class T, int DIM, int NA, int NL>
+__global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T* __restrict__ r,
+                                                  T* __restrict__ out, int npx, int npy, int npz) {
+  constexpr int TS = fdm_tile<NA, NL, DIM>();
+  constexpr int NMAX = imax(NA, NL);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  __shared__ int64_t goff[3][NMAX];
+  __shared__ T wv[3][NMAX];
+  __shared__ T lv[3][NMAX];
+  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+  const int pid = xcd_block(npatch);
+  if (pid < 0) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int NP = L.NP, NE = DIM == 3 ? NP * NP * NP : NP * NP;
+  int p[3];
+  p[0] = pid % npx;
+  p[1] = (pid / npx) % npy;
+  p[2] = DIM == 3 ? pid / (npx * npy) : 0;
+  // tile dimension t -> grid direction gd[t]
+  int gd[3];
+  if (nd < 0) {
+    gd[0] = 0; gd[1] = 1; gd[2] = 2;
+  } else {
+    gd[0] = nd;
+    int q = 1;
+    for (int d = 0; d < DIM; ++d)
+      if (d != nd) gd[q++] = d;
+  }
+  int len[3] = {1, 1, 1};
+  for (int d = 0; d < DIM; ++d) len[d] = (d == nd) ? NA : NL;
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  const int64_t est[3] = {(int64_t)NE, (int64_t)N1 * NE, (int64_t)N1 * N2 * NE};
+  const int nst[3] = {1, NP, NP * NP};
+  // per-direction offset tables, weights and eigenvalues
+  for (int d = 0; d < DIM; ++d) {
+    const DirDev<T>& dd = L.dir[d];
+    const bool fc = d == nd;
+    const int start = fc ? (p[d] - 1) * NP + 1 : p[d] * NP - L.NO;
+    const int G = dd.N * NP;
+    const T* w = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
+    const T* lam = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
+    for (int o = tid; o < len[d]; o += nth) {
+      int g = start + o;
+      int64_t off = -1;
+      if (dd.periodic) g = ((g % G) + G) % G;
+      if (g >= 0 && g < G) {
+        const int mm = g / NP, ii = g - mm * NP;
+        off = mm * est[d] + ii * nst[d];
+      }
+      goff[d][o] = off;
+      wv[d][o] = w[o];
+      lv[d][o] = lam[o];
+    }
+  }
+  __syncthreads();
+  // gather R_s r (grid-natural order for coalesced reads)
+  for (int q = tid; q < TS; q += nth) {
+    int o[3];
+    o[0] = q % len[0];
+    int rest = q / len[0];
+    o[1] = DIM == 3 ? rest % len[1] : rest;
+    o[2] = DIM == 3 ? rest / len[1] : 0;
+    int64_t off = 0;
+    bool ok = true;
+    for (int d = 0; d < DIM; ++d) {
+      const int64_t g = goff[d][o[d]];
+      ok = ok && g >= 0;
+      off += g;
+    }
+    const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
+    tile[(l2 * NL + l1) * NA + a] = ok ? r[off] : T(0);
+  }
+  __syncthreads();
+  const T* S[3];
+  for (int t = 0; t < DIM; ++t) {
+    const int d = gd[t];
+    S[t] = (d == nd) ? L.dir[d].S_fc + (int64_t)p[d] * NA * NA : L.dir[d].S_ec + (int64_t)p[d] * NL * NL;
+  }
+  // forward transform t = (S_3^T x S_2^T x S_1^T) r
+  fdm_pass<T, NA, NL, DIM, true>(tile, 0, S[0]);
+  __syncthreads();
+  fdm_pass<T, NA, NL, DIM, true>(tile, 1, S[1]);
+  __syncthreads();
+  if (DIM == 3) {
+    fdm_pass<T, NA, NL, DIM, true>(tile, 2, S[2]);
+    __syncthreads();
+  }
+  // diagonal scale by the reciprocal sum of 1D eigenvalues
+  for (int q = tid; q < TS; q += nth) {
+    const int a = q % NA, rest = q / NA;
+    const int l1 = DIM == 3 ? rest % NL : rest, l2 = DIM == 3 ? rest / NL : 0;
+    T den = lv[gd[0]][a] + lv[gd[1]][l1];
+    if (DIM == 3) den += lv[gd[2]][l2];
+    tile[q] = tile[q] / den;
+  }
+  __syncthreads();
+  // backward transform
+  if (DIM == 3) {
+    fdm_pass<T, NA, NL, DIM, false>(tile, 2, S[2]);
+    __syncthreads();
+  }
+  fdm_pass<T, NA, NL, DIM, false>(tile, 1, S[1]);
+  __syncthreads();
+  fdm_pass<T, NA, NL, DIM, false>(tile, 0, S[0]);
+  __syncthreads();
+  // weighted result w_s (.) Delta u_s in grid-natural order
+  T* dst = out + (int64_t)pid * TS;
+  for (int q = tid; q < TS; q += nth) {
+    int o[3];
+    o[0] = q % len[0];
+    int rest = q / len[0];
+    o[1] = DIM == 3 ? rest % len[1] : rest;
+    o[2] = DIM == 3 ? rest / len[1] : 0;
+    const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
+    T w = wv[0][o[0]] * wv[1][o[1]];
+    if (DIM == 3) w *= wv[2][o[2]];
+    dst[q] = w * tile[(l2 * NL + l1) * NA + a];
+  }
+}
+
+template <class T, int DIM, int NA, int NL>
+int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
+                 hipStream_t s) {
+  constexpr int TS = fdm_tile<NA, NL, DIM>();
+  const size_t shm = (size_t)TS * sizeof(T);
+  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL>), dim3(xcd_grid(npatch)),
+                     dim3(fdm_threads<NA, NL, DIM>()), shm, s, L, nd, r, out, npx, npy, npz);
+  return 0;
+}
+
+// ================================================================ overlap summation
+// u += sum_s R_s^T (w_s Delta u_s), gathered per node in a fixed order over the
+// (at most 2 x 3 x 3) covering patches: deterministic, no atomics.
+template <class T, int DIM, int NP>
+__global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
+                                                      const T* __restrict__ buf, T* __restrict__ u,
+                                                      int npx, int npy, int npz) {
+  constexpr int NE = ipow(NP, DIM);
+  constexpr int P = NP - 1;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.n_dof) return;
+  const int e = (int)(q / NE), loc = (int)(q - (int64_t)e * NE);
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  int m[3], ii[3], len[3] = {1, 1, 1}, np[3] = {npx, npy, npz};
+  m[0] = e % N1;
+  m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
+  m[2] = DIM == 3 ? e / (N1 * N2) : 0;
+  ii[0] = loc % NP;
+  ii[1] = (loc / NP) % NP;
+  ii[2] = DIM == 3 ? loc / (NP * NP) : 0;
+  int cp[3][3], co[3][3], cn[3] = {1, 1, 1};
+  cp[2][0] = 0;
+  co[2][0] = 0;
+  for (int d = 0; d < DIM; ++d) {
+    const DirDev<T>& dd = L.dir[d];
+    const int N = dd.N;
+    len[d] = (d == nd) ? NA : NL;
+    cn[d] = 0;
+    if (d == nd) {  // faces m (tile position P + i, needs i < P) and m + 1 (position i - 1, needs i >= 1)
+      if (ii[d] < P) {
+        cp[d][cn[d]] = dd.periodic ? m[d] % N : m[d];
+        co[d][cn[d]++] = P + ii[d];
+      }
+      if (ii[d] >= 1) {
+        cp[d][cn[d]] = dd.periodic ? (m[d] + 1) % N : m[d] + 1;
+        co[d][cn[d]++] = ii[d] - 1;
+      }
+    } else {  // element-centred patches m-1, m, m+1
+      const int NO = L.NO;
+      if (ii[d] < NO && (dd.periodic || m[d] > 0)) {
+        cp[d][cn[d]] = (m[d] - 1 + N) % N;
+        co[d][cn[d]++] = NP + NO + ii[d];
+      }
+      cp[d][cn[d]] = m[d];
+      co[d][cn[d]++] = ii[d] + NO;
+      if (ii[d] >= NP - NO && (dd.periodic || m[d] < N - 1)) {
+        cp[d][cn[d]] = (m[d] + 1) % N;
+        co[d][cn[d]++] = ii[d] - NP + NO;
+      }
+    }
+  }
+  const int64_t TS = (int64_t)len[0] * len[1] * len[2];
+  T s = 0;
+  for (int a = 0; a < cn[0]; ++a)
+    for (int b = 0; b < cn[1]; ++b)
+      for (int c = 0; c < cn[2]; ++c) {
+        const int64_t pid = ((int64_t)cp[2][c] * np[1] + cp[1][b]) * np[0] + cp[0][a];
+        const int64_t off = ((int64_t)co[2][c] * len[1] + co[1][b]) * len[0] + co[0][a];
+        s += buf[pid * TS + off];
+      }
+  u[q] += s;
+}
+
+template <class T, int DIM, int NP>
+int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
+                     int npy, int npz, hipStream_t s) {
+  const int TH = 256;
+  const int64_t nb = (L.n_dof + TH - 1) / TH;
+  hipLaunchKernelGGL((combine_kernel<T, DIM, NP>), dim3((unsigned)nb), dim3(TH), 0, s, L, nd, NA,
+                     NL, buf, u, npx, npy, npz);
+  return 0;
+}
+
+// ================================================================ p-transfers
+// Element-local tensor-product contractions with the embedded interpolation J
+// (NPf x NPc).  RESTRICT: out_c = (J^T x J^T x J^T) in_f.  Otherwise:
+// out_f += (J x J x J) in_c.  One block per group of elements; LDS ping-pong.
+template <int NPF, int DIM>
+constexpr int xfer_epb() {
+  return imax(1, 512 / ipow(NPF, DIM));
+}
+
+template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
+__global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, int n_elem,
+                                                       const T* __restrict__ in, T* __restrict__ out) {
+  constexpr int NEF = ipow(NPF, DIM), NEC = ipow(NPC, DIM), EPB = xfer_epb<NPF, DIM>();
+  constexpr int NIN = RESTRICT ? NPF : NPC, NOUT = RESTRICT ? NPC : NPF;
+  constexpr int NEI = ipow(NIN, DIM), NEO = ipow(NOUT, DIM);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* bufA = reinterpret_cast<T*>(smem_raw);
+  T* bufB = bufA + EPB * NEF;
+  const int e0 = blockIdx.x * EPB;
+  const int ne = imin(EPB, n_elem - e0);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < ne * NEI; q += nth) bufA[q] = in[(int64_t)e0 * NEI + q];
+  __syncthreads();
+  // pass over each direction: dims before the pass (out size for done dirs)
+  T* src = bufA;
+  T* dst = bufB;
+  int n0 = NIN, n1 = NIN, n2 = DIM == 3 ? NIN : 1;  // current extents (x fastest)
+#pragma unroll 1
+  for (int d = 0; d < DIM; ++d) {
+    int m0 = n0, m1 = n1, m2 = n2;
+    if (d == 0) m0 = NOUT; else if (d == 1) m1 = NOUT; else m2 = NOUT;
+    const int per = m0 * m1 * m2;
+    for (int q = tid; q < ne * per; q += nth) {
+      const int el = q / per, r = q - el * per;
+      const int i0 = r % m0, i1 = (r / m0) % m1, i2 = r / (m0 * m1);
+      const int iout = d == 0 ? i0 : (d == 1 ? i1 : i2);
+      T s = 0;
+      for (int k = 0; k < NIN; ++k) {
+        const int j0 = d == 0 ? k : i0, j1 = d == 1 ? k : i1, j2 = d == 2 ? k : i2;
+        const T jv = RESTRICT ? J[k * NPC + iout] : J[iout * NPC + k];
+        s += jv * src[el * NEF + (j2 * n1 + j1) * n0 + j0];
+      }
+      dst[el * NEF + r] = s;
+    }
+    __syncthreads();
+    n0 = m0; n1 = m1; n2 = m2;
+    T* tmp = src; src = dst; dst = tmp;
+  }
+  for (int q = tid; q < ne * NEO; q += nth) {
+    const int el = q / NEO, r = q - el * NEO;
+    if (RESTRICT)
+      out[(int64_t)e0 * NEO + q] = src[el * NEF + r];
+    else
+      out[(int64_t)e0 * NEO + q] += src[el * NEF + r];
+  }
+}
+
+template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
+int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, hipStream_t s) {
+  constexpr int EPB = xfer_epb<NPF, DIM>();
+  const int nb = (n_elem + EPB - 1) / EPB;
+  const size_t shm = 2 * (size_t)EPB * ipow(NPF, DIM) * sizeof(T);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)transfer_kernel<T, DIM, NPF, NPC, RESTRICT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT>), dim3(nb), dim3(256), shm, s, J,
+                     n_elem, in, out);
+  return 0;
+}
+
+// ================================================================ dispatch (instantiated per T, DIM)
+template <class T, int DIM>
+struct Kern {
+  static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
+                   int* nblk, hipStream_t s);
+  static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
+                 int npz, hipStream_t s);
+  static bool fdm_supported(int NA, int NL);
+  static int combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
+                     int npy, int npz, hipStream_t s);
+  static int transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, hipStream_t s);
+};
+
+}  // namespace dgmg

@@ -1,0 +1,81 @@
+// Host-side (FP64) construction of every table the device path needs.
+//
+// Sec. 2.4: GLL points and weights, differentiation and stiffness matrices,
+// the global 1D operators of eq. (L:generic) (blocks from eq. (primal form)),
+// Sec. 3.1: per-subdomain generalised eigenpairs and 1D weights,
+// Sec. 3.2: level series and embedded interpolation.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dgmg {
+
+// 1D element coefficients used by the operator kernels, per element m:
+enum ECoef {
+  EC_TWO_DX = 0,  // 2 / dx_m
+  EC_HALF_DX,     // dx_m / 2 (1D mass = HALF_DX * rho_i)
+  EC_CL,          // lift/consistency factor of the left face: (1-2b)/dx_m, or 2/dx_m on a Dirichlet face
+  EC_CNL,         // neighbour-derivative factor at the left face: (1+2b)/dx_{m-1}, 0 on a Dirichlet face
+  EC_BL,          // penalty bracket B_{m-1/2} (mu_b on a Dirichlet face)
+  EC_CR,          // (1+2b)/dx_m, or 2/dx_m on a Dirichlet face
+  EC_CNR,         // (1-2b)/dx_{m+1}, 0 on a Dirichlet face
+  EC_BR,          // B_{m+1/2} (mu_b on a Dirichlet face)
+  EC_COUNT
+};
+
+struct Dir1D {
+  int N = 0;
+  bool periodic = false;
+  std::vector<double> dx;
+  std::vector<double> ecoef;  // N * EC_COUNT
+  std::vector<int> nbr;       // N * 2: left / right neighbour element, -1 at a Dirichlet face
+  // element-centred patches (one per element), tile size n_ec = NP + 2 NO
+  int n_ec = 0;
+  std::vector<double> S_ec, lam_ec, w_ec;  // N * n*n (row-major S[k*n+j]), N*n, N*n
+  // face-centred patches (normal direction), tile size n_fc = 2P
+  int nf = 0, n_fc = 0;
+  std::vector<double> S_fc, lam_fc, w_fc;
+  // global generalised eigenpairs of (L_d, M_d) (coarsest level only), size G = N*NP
+  int G = 0;
+  std::vector<double> S_glob, lam_glob;  // G*G row-major, G
+  int null_mode = -1;                    // index of the zero eigenvalue (periodic), else -1
+};
+
+struct LevelHost {
+  int P = 1, NP = 2, NO = 0, dim = 3;
+  int64_t n_elem = 0, n_dof = 0;
+  std::vector<double> rho, Ls, D;  // NP, NP*NP (row-major), NP*NP (D[i*NP+k] = phi_k'(eta_i))
+  std::vector<double> J;           // NP x NPc interpolation from the next coarser level (row-major)
+  int NPc = 0;
+  Dir1D dir[3];
+};
+
+struct SetupParams {
+  int dim = 3;
+  int n[3] = {1, 1, 1};
+  std::vector<double> dx[3];
+  bool periodic[3] = {false, false, false};
+  int P = 4;
+  int flux = 0;
+  double beta[3] = {0, 0, 0};
+  double mu_star = 1.0;
+  int smoother = 1;
+  int overlap = -1;
+  int weighting = 0;
+};
+
+// Builds all levels (index 0 = coarsest, P = 1).  Returns an empty string on
+// success, else an error message.
+std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels);
+
+// Primitives (exposed for the host self-checks).
+void gll_points(int P, std::vector<double>& eta, std::vector<double>& rho);
+void gll_diff(int P, const std::vector<double>& eta, std::vector<double>& D);
+int overlap_rule(int P_l, int overlap);
+// Symmetric eigen-decomposition by the cyclic Jacobi method: A (n*n, row-major,
+// destroyed) -> eigenvalues lam, eigenvectors as columns of V (row-major).
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
+
+}  // namespace dgmg

@@ -1,0 +1,106 @@
+"""The C-ABI library loads, exports every entry point declared in include/dgmg.h,
+and its host-side setup validates arguments and matches the oracle's geometry.
+No device work is started here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_1603_02524_amd import dgmg as D
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgmg.h")
+
+
+def _header_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(dgmg_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = D.load_library()
+    syms = _header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(n for n, _, _ in D.SIGNATURES) == syms
+
+
+def test_struct_layouts_match_header():
+    # dgmg_stats holds 256 history entries; sizes follow the C declaration order
+    assert ctypes.sizeof(D.DgmgStats) == 4 + 4 + 8 * 3 + 8 * 256
+    # int dim; int n_elem[3]; const double* dx[3] (8-aligned at 16); int periodic[3]; tail pad
+    assert ctypes.sizeof(D.DgmgGrid) == 56
+    assert ctypes.sizeof(D.DgmgOpts) == 4 + 4 + 24 + 8 + 4 * 8
+
+
+def test_defaults():
+    lib = D.load_library()
+    o = D.DgmgOpts()
+    assert lib.dgmg_opts_default(ctypes.byref(o)) == 0
+    assert o.P == 4 and o.mu_star == 1.0 and o.ns_pre == 1 and o.ns_post == 1 and o.overlap == -1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(P=5), dict(P=0), dict(mu_star=0.0), dict(mu_star=-1.0), dict(smoother="XX"),
+])
+def test_setup_rejects_bad_options(bad):
+    g = synth.uniform_grid(3, 2, 1.0, False)
+    m = synth.Method(P=4)
+    for k, v in bad.items():
+        setattr(m, k, v)
+    if bad.get("smoother") == "XX":
+        with pytest.raises(KeyError):
+            D.setup_handle(g, m)
+        return
+    with pytest.raises(D.DgmgError) as ei:
+        D.setup_handle(g, m)
+    assert ei.value.code < 0
+
+
+def test_setup_rejects_bad_grid():
+    m = synth.Method(P=4)
+    g = synth.Grid(3, (np.array([0.5, -0.5]), np.ones(2), np.ones(2)), (False,) * 3)
+    with pytest.raises(D.DgmgError):
+        D.setup_handle(g, m)
+    g = synth.Grid(3, (np.array([0.5, np.nan]), np.ones(2), np.ones(2)), (False,) * 3)
+    with pytest.raises(D.DgmgError):
+        D.setup_handle(g, m)
+    g = synth.uniform_grid(3, 2, 1.0, True)          # periodic needs >= 3 elements
+    with pytest.raises(D.DgmgError):
+        D.setup_handle(g, m)
+    g = synth.uniform_grid(2, 3, 1.0, False)
+    with pytest.raises(D.DgmgError):
+        D.setup_handle(g, synth.Method(P=4, flux="ldg", beta=(2.0, 0.0)))
+
+
+def test_level_series_and_geometry_match_oracle():
+    from oracle import multigrid as mg
+    from oracle import operator as op
+    from oracle.schwarz import overlap_for
+    lib = D.load_library()
+    rng = np.random.default_rng(0)
+    g = synth.Grid(3, tuple(rng.uniform(0.2, 1.0, 3) for _ in range(3)), (False,) * 3)
+    for P in (1, 2, 3, 4, 6, 8, 12, 16):
+        for ov in ("level", "level_floor", "zero"):
+            m = synth.Method(P=P, smoother="FA", overlap=ov)
+            h, keep = D.setup_handle(g, m)
+            try:
+                orders = mg.level_orders(P)
+                assert lib.dgmg_num_levels(h) == len(orders)
+                for l, Pl in enumerate(orders):
+                    Pc, no, nd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+                    assert lib.dgmg_level_info(h, l, ctypes.byref(Pc), ctypes.byref(no), ctypes.byref(nd)) == 0
+                    assert Pc.value == Pl and nd.value == g.n_elem * (Pl + 1) ** 3
+                    assert no.value == (overlap_for(Pl, ov) if l > 0 else 0)
+                    x = np.zeros(3 * (Pl + 1))
+                    assert lib.dgmg_node_coords(h, l, 0, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+                    assert np.allclose(x, op.node_coords_1d(np.asarray(g.dx[0]), Pl), atol=1e-15)
+                # device entry points refuse to run before a workspace is bound
+                assert lib.dgmg_apply(h, 0, ctypes.c_void_p(8), ctypes.c_void_p(16), 0) == D.DgmgError(-3, "").code
+                assert b"workspace" in lib.dgmg_last_error(h)
+            finally:
+                lib.dgmg_destroy(h)
