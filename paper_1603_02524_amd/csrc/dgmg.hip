@@ -304,6 +304,16 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, std::vector<std
     dd.ecoef = put(s.ecoef);
     dd.nbr = put_int(s.nbr);
     if (!s.S_ec.empty()) {
+      auto transp = [](const std::vector<double>& S, int n) {
+        std::vector<double> t(S.size());
+        const size_t nb = S.size() / ((size_t)n * n);
+        for (size_t b = 0; b < nb; ++b)
+          for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) t[b * n * n + (size_t)j * n + i] = S[b * n * n + (size_t)i * n + j];
+        return t;
+      };
+      dd.ST_ec = put(transp(s.S_ec, s.n_ec));
+      dd.ST_fc = put(transp(s.S_fc, s.n_fc));
       dd.S_ec = put(s.S_ec);
       dd.lam_ec = put(s.lam_ec);
       dd.w_ec = put(s.w_ec);

@@ -38,9 +38,11 @@ struct DirDev {
   const T* ecoef = nullptr;  // N * 8 (see ECOEF enum)
   const int* nbr = nullptr;  // N * 2
   const T* S_ec = nullptr;   // N * n_ec^2, row-major S[k][j]
+  const T* ST_ec = nullptr;  // the transposes
   const T* lam_ec = nullptr;
   const T* w_ec = nullptr;
   const T* S_fc = nullptr;   // nf * n_fc^2
+  const T* ST_fc = nullptr;
   const T* lam_fc = nullptr;
   const T* w_fc = nullptr;
 };
@@ -234,50 +236,114 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
 }
 
 // ================================================================ FDM patch solve
-// One patch per block.  The LDS tile is stored with the normal direction
-// fastest: tile[(l2 * NL + l1) * NA + a]; NA = 2P (face-centred normal) or the
-// element-centred size, NL = lateral size NP + 2 N_O.  Each contraction pass
-// gives every thread whole lines (kept in registers) and overwrites them in
-// place, so one tile suffices.
+// One patch per block.  The LDS tile keeps the normal direction fastest:
+// tile[(l2 * NL + l1) * NAP + a], NAP = NA rounded up to an odd pitch so that
+// the lines of the fastest pass spread over the LDS banks.  NA = 2P for a
+// face-centred patch (the element-centred size otherwise), NL = NP + 2 N_O.
+// Each contraction pass runs on the matrix cores: the lines of the tile are the
+// M dimension (blocks of 16), the 1D eigenbasis is the B operand held in
+// registers, and each wave overwrites its line blocks in place.
 template <int NA, int NL, int DIM>
 constexpr int fdm_tile() {
   return NA * ipow(NL, DIM - 1);
+}
+template <int NA>
+constexpr int fdm_pitch() {
+  return NA % 2 == 0 ? NA + 1 : NA;
+}
+template <int NA, int NL, int DIM>
+constexpr int fdm_tile_padded() {
+  return fdm_pitch<NA>() * ipow(NL, DIM - 1);
 }
 template <int NA, int NL, int DIM>
 constexpr int fdm_threads() {
   return imin(256, round64(imax(ipow(NL, DIM - 1), NA * ipow(NL, DIM - 2))));
 }
-
-template <class T, int LEN, bool FWD>
-__device__ __forceinline__ void fdm_line(T* __restrict__ tile, int base, int stride,
-                                         const T* __restrict__ S) {
-  T v[LEN];
-#pragma unroll
-  for (int k = 0; k < LEN; ++k) v[k] = tile[base + k * stride];
-#pragma unroll
-  for (int j = 0; j < LEN; ++j) {
-    T acc = 0;
-#pragma unroll
-    for (int k = 0; k < LEN; ++k) acc += (FWD ? S[k * LEN + j] : S[j * LEN + k]) * v[k];
-    tile[base + j * stride] = acc;
-  }
+template <class T, int NA, int NL, int DIM>
+constexpr size_t fdm_shmem() {
+  return (size_t)fdm_tile_padded<NA, NL, DIM>() * sizeof(T);
 }
 
-template <class T, int NA, int NL, int DIM, bool FWD>
-__device__ __forceinline__ void fdm_pass(T* tile, int t, const T* __restrict__ S) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  if (t == 0) {
-    constexpr int LINES = ipow(NL, DIM - 1);
-    for (int ln = tid; ln < LINES; ln += nth) fdm_line<T, NA, FWD>(tile, ln * NA, 1, S);
-  } else if (t == 1) {
-    constexpr int LINES = NA * ipow(NL, DIM - 2);
-    for (int ln = tid; ln < LINES; ln += nth) {
-      const int a = ln % NA, l2 = ln / NA;
-      fdm_line<T, NL, FWD>(tile, l2 * NA * NL + a, NA, S);
+// 16x16x4 matrix-core contraction (v_mfma_{f64,f32}_16x16x4): A[i][k] comes from lane
+// i + 16k and B[k][j] from lane j + 16k.  Result register r of lane l holds
+// D[row(l / 16, r)][l % 16] with row = l/16 + 4r for f64 and 4 (l/16) + r for f32
+// (layouts checked on gfx950 with one-hot operands).
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// Line start inside the padded tile for contraction dimension TD.
+template <int NA, int NL, int TD>
+__device__ __forceinline__ int fdm_line_base(int line) {
+  constexpr int NAP = fdm_pitch<NA>();
+  if (TD == 0) return line * NAP;
+  const int a = line % NA, q = line / NA;
+  return TD == 1 ? q * NAP * NL + a : q * NAP + a;
+}
+
+// One contraction pass over tile dimension TD: every line v (length LEN) is
+// replaced by B^T v, i.e. out_j = sum_k B[k][j] v_k, with B row-major (LEN x LEN)
+// in global memory.  The lines form the M dimension in blocks of 16; each wave
+// owns whole blocks, reads them (A operand) and writes them back in place.
+template <class T, int NA, int NL, int DIM, int TD>
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm) {
+  constexpr int NAP = fdm_pitch<NA>();
+  constexpr int LEN = TD == 0 ? NA : NL;
+  constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
+  constexpr int STRIDE = TD == 0 ? 1 : (TD == 1 ? NAP : NAP * NL);
+  constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16, MB = (LINES + 15) / 16;
+  using M = Mfma<T>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  T b[NB][KS];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + lk, j = nb * 16 + li;
+      b[nb][ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
     }
-  } else {
-    constexpr int LINES = NA * NL;
-    for (int ln = tid; ln < LINES; ln += nth) fdm_line<T, NL, FWD>(tile, ln, NA * NL, S);
+  for (int mb = wave; mb < MB; mb += nw) {
+    const int line = mb * 16 + li;
+    const bool lv = line < LINES;
+    const int base = lv ? fdm_line_base<NA, NL, TD>(line) : 0;
+    typename M::acc_t acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename M::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + lk;
+      const T a = (lv && k < LEN) ? tile[base + k * STRIDE] : T(0);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, b[nb][ks], acc[nb]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int oline = mb * 16 + M::row(lk, r);
+      if (oline < LINES) {
+        const int ob = fdm_line_base<NA, NL, TD>(oline);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int j = nb * 16 + li;
+          if (j < LEN) tile[ob + j * STRIDE] = acc[nb][r];
+        }
+      }
+    }
   }
 }
 
@@ -285,6 +351,7 @@ template <class T, int DIM, int NA, int NL>
 __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T* __restrict__ r,
                                                   T* __restrict__ out, int npx, int npy, int npz) {
   constexpr int TS = fdm_tile<NA, NL, DIM>();
+  constexpr int NAP = fdm_pitch<NA>();
   constexpr int NMAX = imax(NA, NL);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
@@ -300,8 +367,7 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   p[0] = pid % npx;
   p[1] = (pid / npx) % npy;
   p[2] = DIM == 3 ? pid / (npx * npy) : 0;
-  // tile dimension t -> grid direction gd[t]
-  int gd[3];
+  int gd[3];  // tile dimension t -> grid direction
   if (nd < 0) {
     gd[0] = 0; gd[1] = 1; gd[2] = 2;
   } else {
@@ -315,7 +381,6 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   const int64_t est[3] = {(int64_t)NE, (int64_t)N1 * NE, (int64_t)N1 * N2 * NE};
   const int nst[3] = {1, NP, NP * NP};
-  // per-direction offset tables, weights and eigenvalues
   for (int d = 0; d < DIM; ++d) {
     const DirDev<T>& dd = L.dir[d];
     const bool fc = d == nd;
@@ -336,12 +401,27 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
       lv[d][o] = lam[o];
     }
   }
+  // 1D matrices of each tile dimension: forward t_j = sum_k S_kj r_k uses S,
+  // backward u_k = sum_j S_kj t_j uses S^T (both row-major)
+  const T* fwd[3] = {nullptr, nullptr, nullptr};
+  const T* bwd[3] = {nullptr, nullptr, nullptr};
+  for (int t = 0; t < DIM; ++t) {
+    const int d = gd[t];
+    const DirDev<T>& dd = L.dir[d];
+    if (d == nd) {
+      fwd[t] = dd.S_fc + (int64_t)p[d] * NA * NA;
+      bwd[t] = dd.ST_fc + (int64_t)p[d] * NA * NA;
+    } else {
+      fwd[t] = dd.S_ec + (int64_t)p[d] * NL * NL;
+      bwd[t] = dd.ST_ec + (int64_t)p[d] * NL * NL;
+    }
+  }
   __syncthreads();
-  // gather R_s r (grid-natural order for coalesced reads)
+  // gather R_s r (grid-natural order: coalesced global reads)
   for (int q = tid; q < TS; q += nth) {
     int o[3];
     o[0] = q % len[0];
-    int rest = q / len[0];
+    const int rest = q / len[0];
     o[1] = DIM == 3 ? rest % len[1] : rest;
     o[2] = DIM == 3 ? rest / len[1] : 0;
     int64_t off = 0;
@@ -352,21 +432,15 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
       off += g;
     }
     const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
-    tile[(l2 * NL + l1) * NA + a] = ok ? r[off] : T(0);
+    tile[(l2 * NL + l1) * NAP + a] = ok ? r[off] : T(0);
   }
   __syncthreads();
-  const T* S[3];
-  for (int t = 0; t < DIM; ++t) {
-    const int d = gd[t];
-    S[t] = (d == nd) ? L.dir[d].S_fc + (int64_t)p[d] * NA * NA : L.dir[d].S_ec + (int64_t)p[d] * NL * NL;
-  }
-  // forward transform t = (S_3^T x S_2^T x S_1^T) r
-  fdm_pass<T, NA, NL, DIM, true>(tile, 0, S[0]);
+  fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
   __syncthreads();
-  fdm_pass<T, NA, NL, DIM, true>(tile, 1, S[1]);
+  fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
   __syncthreads();
-  if (DIM == 3) {
-    fdm_pass<T, NA, NL, DIM, true>(tile, 2, S[2]);
+  if constexpr (DIM == 3) {
+    fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2]);
     __syncthreads();
   }
   // diagonal scale by the reciprocal sum of 1D eigenvalues
@@ -375,42 +449,41 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
     const int l1 = DIM == 3 ? rest % NL : rest, l2 = DIM == 3 ? rest / NL : 0;
     T den = lv[gd[0]][a] + lv[gd[1]][l1];
     if (DIM == 3) den += lv[gd[2]][l2];
-    tile[q] = tile[q] / den;
+    const int idx = (l2 * NL + l1) * NAP + a;
+    tile[idx] = tile[idx] / den;
   }
   __syncthreads();
-  // backward transform
-  if (DIM == 3) {
-    fdm_pass<T, NA, NL, DIM, false>(tile, 2, S[2]);
+  if constexpr (DIM == 3) {
+    fdm_pass<T, NA, NL, DIM, 2>(tile, bwd[2]);
     __syncthreads();
   }
-  fdm_pass<T, NA, NL, DIM, false>(tile, 1, S[1]);
+  fdm_pass<T, NA, NL, DIM, 1>(tile, bwd[1]);
   __syncthreads();
-  fdm_pass<T, NA, NL, DIM, false>(tile, 0, S[0]);
+  fdm_pass<T, NA, NL, DIM, 0>(tile, bwd[0]);
   __syncthreads();
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
   for (int q = tid; q < TS; q += nth) {
     int o[3];
     o[0] = q % len[0];
-    int rest = q / len[0];
+    const int rest = q / len[0];
     o[1] = DIM == 3 ? rest % len[1] : rest;
     o[2] = DIM == 3 ? rest / len[1] : 0;
     const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
     T w = wv[0][o[0]] * wv[1][o[1]];
     if (DIM == 3) w *= wv[2][o[2]];
-    dst[q] = w * tile[(l2 * NL + l1) * NA + a];
+    dst[q] = w * tile[(l2 * NL + l1) * NAP + a];
   }
 }
 
 template <class T, int DIM, int NA, int NL>
 int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
                  hipStream_t s) {
-  constexpr int TS = fdm_tile<NA, NL, DIM>();
-  const size_t shm = (size_t)TS * sizeof(T);
+  constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL>), dim3(xcd_grid(npatch)),
                      dim3(fdm_threads<NA, NL, DIM>()), shm, s, L, nd, r, out, npx, npy, npz);
   return 0;
@@ -418,74 +491,83 @@ int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int 
 
 // ================================================================ overlap summation
 // u += sum_s R_s^T (w_s Delta u_s), gathered per node in a fixed order over the
-// (at most 2 x 3 x 3) covering patches: deterministic, no atomics.
+// (at most 2 x 3 x 3) covering patches: deterministic, no atomics.  One block
+// per group of elements; per element and direction the candidate patches of
+// each local index are tabulated in LDS as address components, so a node's sum
+// is a few loads at addresses Ax[i] + Ay[j] + Az[k].
+template <int NP, int DIM>
+constexpr int combine_epb() {
+  return imax(1, 256 / ipow(NP, DIM));
+}
+
 template <class T, int DIM, int NP>
 __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
                                                       const T* __restrict__ buf, T* __restrict__ u,
-                                                      int npx, int npy, int npz) {
-  constexpr int NE = ipow(NP, DIM);
+                                                      int npx, int npy, int npz, int nblk) {
+  constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>();
   constexpr int P = NP - 1;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= L.n_dof) return;
-  const int e = (int)(q / NE), loc = (int)(q - (int64_t)e * NE);
-  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
-  int m[3], ii[3], len[3] = {1, 1, 1}, np[3] = {npx, npy, npz};
-  m[0] = e % N1;
-  m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
-  m[2] = DIM == 3 ? e / (N1 * N2) : 0;
-  ii[0] = loc % NP;
-  ii[1] = (loc / NP) % NP;
-  ii[2] = DIM == 3 ? loc / (NP * NP) : 0;
-  int cp[3][3], co[3][3], cn[3] = {1, 1, 1};
-  cp[2][0] = 0;
-  co[2][0] = 0;
-  for (int d = 0; d < DIM; ++d) {
+  __shared__ int64_t cadr[EPB][3][NP][3];
+  __shared__ int ccnt[EPB][3][NP];
+  const int blk = xcd_block(nblk);
+  if (blk < 0) return;
+  const int e0 = blk * EPB;
+  const int ne = imin(EPB, L.n_elem - e0);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N, NO = L.NO;
+  int len[3] = {1, 1, 1};
+  for (int d = 0; d < DIM; ++d) len[d] = (d == nd) ? NA : NL;
+  const int64_t TS = (int64_t)len[0] * len[1] * len[2];
+  const int64_t pst[3] = {1, npx, (int64_t)npx * npy};
+  const int64_t ost[3] = {1, len[0], (int64_t)len[0] * len[1]};
+  for (int q = tid; q < ne * DIM * NP; q += nth) {
+    const int el = q / (DIM * NP), rem = q - el * DIM * NP, d = rem / NP, i = rem - d * NP;
+    const int e = e0 + el;
+    const int md = d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
     const DirDev<T>& dd = L.dir[d];
     const int N = dd.N;
-    len[d] = (d == nd) ? NA : NL;
-    cn[d] = 0;
+    int c = 0;
+    int cp[3], co[3];
     if (d == nd) {  // faces m (tile position P + i, needs i < P) and m + 1 (position i - 1, needs i >= 1)
-      if (ii[d] < P) {
-        cp[d][cn[d]] = dd.periodic ? m[d] % N : m[d];
-        co[d][cn[d]++] = P + ii[d];
-      }
-      if (ii[d] >= 1) {
-        cp[d][cn[d]] = dd.periodic ? (m[d] + 1) % N : m[d] + 1;
-        co[d][cn[d]++] = ii[d] - 1;
-      }
-    } else {  // element-centred patches m-1, m, m+1
-      const int NO = L.NO;
-      if (ii[d] < NO && (dd.periodic || m[d] > 0)) {
-        cp[d][cn[d]] = (m[d] - 1 + N) % N;
-        co[d][cn[d]++] = NP + NO + ii[d];
-      }
-      cp[d][cn[d]] = m[d];
-      co[d][cn[d]++] = ii[d] + NO;
-      if (ii[d] >= NP - NO && (dd.periodic || m[d] < N - 1)) {
-        cp[d][cn[d]] = (m[d] + 1) % N;
-        co[d][cn[d]++] = ii[d] - NP + NO;
+      if (i < P) { cp[c] = md; co[c++] = P + i; }
+      if (i >= 1) { cp[c] = dd.periodic ? (md + 1) % N : md + 1; co[c++] = i - 1; }
+    } else {        // element-centred patches m - 1, m, m + 1
+      if (i < NO && (dd.periodic || md > 0)) { cp[c] = (md - 1 + N) % N; co[c++] = NP + NO + i; }
+      cp[c] = md; co[c++] = i + NO;
+      if (i >= NP - NO && (dd.periodic || md < N - 1)) { cp[c] = (md + 1) % N; co[c++] = i - NP + NO; }
+    }
+    ccnt[el][d][i] = c;
+    for (int k = 0; k < c; ++k) cadr[el][d][i][k] = cp[k] * pst[d] * TS + co[k] * ost[d];
+  }
+  if (DIM == 2)
+    for (int q = tid; q < ne; q += nth) {
+      ccnt[q][2][0] = 1;
+      cadr[q][2][0][0] = 0;
+    }
+  __syncthreads();
+  const int64_t g0 = (int64_t)e0 * NE;
+  for (int q = tid; q < ne * NE; q += nth) {
+    const int el = q / NE, loc = q - el * NE;
+    const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
+    const int nx = ccnt[el][0][i], ny = ccnt[el][1][j], nz = ccnt[el][2][k];
+    T s = 0;
+    for (int c = 0; c < nz; ++c) {
+      const int64_t az = cadr[el][2][k][c];
+      for (int b = 0; b < ny; ++b) {
+        const int64_t ayz = az + cadr[el][1][j][b];
+        for (int a = 0; a < nx; ++a) s += buf[ayz + cadr[el][0][i][a]];
       }
     }
+    u[g0 + q] += s;
   }
-  const int64_t TS = (int64_t)len[0] * len[1] * len[2];
-  T s = 0;
-  for (int a = 0; a < cn[0]; ++a)
-    for (int b = 0; b < cn[1]; ++b)
-      for (int c = 0; c < cn[2]; ++c) {
-        const int64_t pid = ((int64_t)cp[2][c] * np[1] + cp[1][b]) * np[0] + cp[0][a];
-        const int64_t off = ((int64_t)co[2][c] * len[1] + co[1][b]) * len[0] + co[0][a];
-        s += buf[pid * TS + off];
-      }
-  u[q] += s;
 }
 
 template <class T, int DIM, int NP>
 int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, hipStream_t s) {
-  const int TH = 256;
-  const int64_t nb = (L.n_dof + TH - 1) / TH;
-  hipLaunchKernelGGL((combine_kernel<T, DIM, NP>), dim3((unsigned)nb), dim3(TH), 0, s, L, nd, NA,
-                     NL, buf, u, npx, npy, npz);
+  constexpr int EPB = combine_epb<NP, DIM>();
+  const int nblk = (L.n_elem + EPB - 1) / EPB;
+  hipLaunchKernelGGL((combine_kernel<T, DIM, NP>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
+                     NL, buf, u, npx, npy, npz, nblk);
   return 0;
 }
 
@@ -510,7 +592,10 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
   const int e0 = blockIdx.x * EPB;
   const int ne = imin(EPB, n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int q = tid; q < ne * NEI; q += nth) bufA[q] = in[(int64_t)e0 * NEI + q];
+  for (int q = tid; q < ne * NEI; q += nth) {
+    const int el = q / NEI, r = q - el * NEI;
+    bufA[el * NEF + r] = in[(int64_t)e0 * NEI + q];  // per-element stride NEF in LDS
+  }
   __syncthreads();
   // pass over each direction: dims before the pass (out size for done dirs)
   T* src = bufA;
