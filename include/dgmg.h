@@ -79,6 +79,7 @@ extern "C" {
 #define DGMG_PREC_MIXED 1 /* V-cycle in float (coarse solve in double) inside FP64 PCG */
 
 typedef struct dgmg_handle dgmg_handle;
+typedef struct dgmg_batch dgmg_batch;
 
 /* Cartesian grid (Sec. 2.2).  dx[d] points to n_elem[d] HOST doubles > 0. */
 typedef struct {
@@ -204,12 +205,59 @@ int dgmg_kernel_timing(dgmg_handle* h, int enable);
 int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double* flops,
                      double* bytes);
 
+/* Replay the two per-iteration phases of dgmg_solve (operator + update; V-cycle +
+ * direction update) from hipGraphs captured on first use (enable != 0), or
+ * launch them eagerly (0, the default).  Graphs are recaptured when x, the
+ * stream or a tuning choice changes. */
+int dgmg_use_graphs(dgmg_handle* h, int enable);
+
+/* Autotuner: time the patch-solve block shapes (1, 2 or 4 wavefronts per
+ * patch) of every smoothing sweep on the bound workspace and keep the fastest
+ * (synchronises; results are bitwise independent of the choice).
+ * dgmg_tune_get/set read or impose the choice for (level >= 1, kind), kind
+ * 0..2 = face-centred sweep normal to direction kind, 3 = element-centred;
+ * waves 0 = built-in default.  ms: mean time of one launch when timed. */
+int dgmg_autotune(dgmg_handle* h);
+int dgmg_tune_get(const dgmg_handle* h, int level, int kind, int* waves, double* ms);
+int dgmg_tune_set(dgmg_handle* h, int level, int kind, int waves);
+
 /* Release host tables and HIP objects of the handle (not the workspace). */
 void dgmg_destroy(dgmg_handle* h);
 
 /* Message of the last failure on h (or of the last failed dgmg_setup when h
  * is NULL).  The string is owned by the library. */
 const char* dgmg_last_error(const dgmg_handle* h);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent grids (own sizes, orders, options) solved together:
+ * MGCG runs in lock step with one host synchronisation per iteration for all
+ * grids; each phase of an iteration is one hipGraph whose per-grid chains are
+ * independent (captured once, replayed; converged grids are masked by a
+ * device flag that every kernel checks).  Vectors of all grids are
+ * concatenated (FP64, element-major per grid) at the offsets reported by
+ * dgmg_batch_offsets.  Extension beyond the paper (many-grid throughput). */
+
+/* Set up `count` grids (host work only); grids[i], opts[i] as for dgmg_setup. */
+int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, dgmg_batch** out);
+int dgmg_batch_workspace_bytes(const dgmg_batch* b, size_t* bytes);
+/* Bind one caller-allocated device workspace (256-byte aligned) for all grids. */
+int dgmg_batch_bind_workspace(dgmg_batch* b, void* dev, size_t bytes, void* stream);
+/* Host array of count + 1 offsets of each grid's unknowns in the concatenation. */
+int dgmg_batch_offsets(const dgmg_batch* b, int64_t* offsets);
+/* Borrow the handle of grid i (level operations on one grid; do not destroy,
+ * do not call dgmg_solve on it). */
+int dgmg_batch_handle(dgmg_batch* b, int i, dgmg_handle** h);
+/* Autotune every grid's sweeps (shapes with identical tiles and patch counts
+ * are timed once). */
+int dgmg_batch_autotune(dgmg_batch* b);
+/* Graph replay on (default) or eager per-grid launches. */
+int dgmg_batch_use_graphs(dgmg_batch* b, int enable);
+/* Solve all grids to ||r_i|| <= tol ||r_i,0|| (each grid's own max_iter);
+ * st: host array of count dgmg_stats (may be NULL).  DGMG_NOT_CONVERGED if
+ * any grid stopped unconverged. */
+int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dgmg_stats* st);
+const char* dgmg_batch_last_error(const dgmg_batch* b);
+void dgmg_batch_destroy(dgmg_batch* b);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,8 @@ constexpr int VEC_THREADS = 256;
 // ---------------------------------------------------------------- vector kernels (FP64 PCG)
 __global__ void __launch_bounds__(VEC_THREADS) k_dot(const double* __restrict__ a,
                                                      const double* __restrict__ b, int64_t n,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, const int* act) {
+  if (inactive(act)) return;
   __shared__ double red[16];
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -43,7 +44,8 @@ __global__ void __launch_bounds__(VEC_THREADS) k_dot(const double* __restrict__ 
 
 // Sum of partials in a fixed order into out[0] (one block).
 __global__ void __launch_bounds__(VEC_THREADS) k_finalize(const double* __restrict__ part, int np,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out, const int* act) {
+  if (inactive(act)) return;
   __shared__ double red[16];
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
@@ -56,7 +58,8 @@ __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const double* __restrict
                                                         const double* __restrict__ r,
                                                         const double* __restrict__ ro, int64_t n,
                                                         double* __restrict__ part1,
-                                                        double* __restrict__ part2) {
+                                                        double* __restrict__ part2, const int* act) {
+  if (inactive(act)) return;
   __shared__ double red[16];
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -79,7 +82,8 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
                                                            const double* __restrict__ q,
                                                            const double* __restrict__ delta,
                                                            const double* __restrict__ pq, int64_t n,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part, const int* act) {
+  if (inactive(act)) return;
   __shared__ double red[16];
   const double alpha = delta[0] / pq[0];
   double s = 0.0;
@@ -99,7 +103,8 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p
                                                           double* __restrict__ ro,
                                                           const double* __restrict__ num,
                                                           const double* __restrict__ delta_old,
-                                                          int64_t n) {
+                                                          int64_t n, const int* act) {
+  if (inactive(act)) return;
   const double beta = num[0] / delta_old[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     p[i] = z[i] + beta * p[i];
@@ -108,25 +113,29 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p
 }
 
 template <class A, class B>
-__global__ void __launch_bounds__(VEC_THREADS) k_convert(const A* __restrict__ a, B* __restrict__ b, int64_t n) {
+__global__ void __launch_bounds__(VEC_THREADS) k_convert(const A* __restrict__ a, B* __restrict__ b, int64_t n, const int* act) {
+  if (inactive(act)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = (B)a[i];
 }
 
 template <class T>
-__global__ void __launch_bounds__(VEC_THREADS) k_fill(T* __restrict__ a, T v, int64_t n) {
+__global__ void __launch_bounds__(VEC_THREADS) k_fill(T* __restrict__ a, T v, int64_t n, const int* act) {
+  if (inactive(act)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
 
-__global__ void __launch_bounds__(VEC_THREADS) k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+__global__ void __launch_bounds__(VEC_THREADS) k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n, const int* act) {
+  if (inactive(act)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
 }
 
 // a -= s[0] * scale
 __global__ void __launch_bounds__(VEC_THREADS) k_sub_scalar(double* __restrict__ a, const double* __restrict__ s,
-                                                            double scale, int64_t n) {
+                                                            double scale, int64_t n, const int* act) {
+  if (inactive(act)) return;
   const double v = s[0] * scale;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] -= v;
@@ -160,7 +169,9 @@ struct CoarseDev {
 
 template <bool FWD, bool SCALE>
 __global__ void __launch_bounds__(VEC_THREADS) k_coarse_pass(CoarseDev C, int d, const double* __restrict__ in,
-                                                             double* __restrict__ out, int64_t n) {
+                                                             double* __restrict__ out, int64_t n,
+                                                             const int* act) {
+  if (inactive(act)) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int dim = C.dim, NE = dim == 3 ? 8 : 4;
@@ -195,6 +206,9 @@ inline unsigned vec_blocks(int64_t n) {
 }  // namespace
 
 // =================================================================== handle
+constexpr int MAXL = 8;      // levels: P <= 16 gives at most 6
+constexpr int NKIND = 4;     // sweep kinds: 0..2 face-centred normal d, 3 element-centred
+
 struct dgmg_handle {
   SetupParams sp;
   dgmg_opts opts;
@@ -212,22 +226,51 @@ struct dgmg_handle {
     void* f = nullptr;
     void* r = nullptr;
   };
-  std::vector<Bufs> buf;  // per level, MG precision
-  void* patch = nullptr;  // patch buffer (MG precision), also used by dgmg_smooth in either precision
+  std::vector<Bufs> buf;  // per level, multigrid precision (r sized for doubles)
+  void* patch = nullptr;  // patch buffer (sized for doubles)
   size_t patch_elems = 0;
-  double *c_a = nullptr, *c_b = nullptr, *c_f = nullptr;  // coarse FDM scratch (FP64)
+  double *c_a = nullptr, *c_b = nullptr, *c_f = nullptr;  // coarse FDM scratch
   CoarseDev cdev{};
   // PCG (top level, FP64)
   double *pr = nullptr, *pro = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;
-  double* part = nullptr;   // 2 * RED_BLOCKS
-  double* scal = nullptr;   // scalar slots
-  double* host_scal = nullptr;  // pinned
-  // timing
+  double *part = nullptr, *part2 = nullptr;  // reduction partials
+  double* scal = nullptr;                    // slots: 0 delta, 2 p.q, 3 r.r, 4 z.(r-r_old), 5 z.r
+  double* host_scal = nullptr;               // pinned
+  // batched use: device flag (kernels return when 0) and the slot receiving r.r
+  const int* active = nullptr;
+  double* rr_out = nullptr;
+  // hipGraph replay of the PCG phases
+  bool use_graphs = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const double* graph_x = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only while capturing
+  // autotuned patch-solve block shapes (waves per block), 0 = default
+  int waves[MAXL][NKIND] = {};
+  float tune_ms[MAXL][NKIND] = {};
+  // timing of the top-level patch solves
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   std::vector<double> ev_flops, ev_bytes;
   double t_ms = 0, t_flops = 0, t_bytes = 0;
   int64_t t_launch = 0;
+};
+
+struct dgmg_batch {
+  std::vector<dgmg_handle*> h;
+  std::vector<size_t> sub_off;
+  std::vector<int64_t> dof_off;
+  size_t ws_need = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int* flags_dev = nullptr;
+  double* rr_dev = nullptr;
+  int* flags_host = nullptr;
+  double* rr_host = nullptr;
+  bool bound = false;
+  bool use_graphs = true;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const double* graph_x = nullptr;
+  std::string err;
 };
 
 namespace {
@@ -259,8 +302,10 @@ struct Carver {
   }
 };
 
+using Upload = std::vector<std::pair<void*, std::vector<char>>>;
+
 template <class T>
-void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, std::vector<std::pair<void*, std::vector<char>>>* up) {
+void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
   auto put = [&](const std::vector<double>& v) -> const T* {
     void* p = cv.take(v.size() * sizeof(T));
     if (up && p) {
@@ -279,6 +324,14 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, std::vector<std
       up->emplace_back(p, std::move(bytes));
     }
     return (const int*)p;
+  };
+  auto transp = [](const std::vector<double>& S, int n) {
+    std::vector<double> t(S.size());
+    const size_t nb = S.size() / ((size_t)n * n);
+    for (size_t b = 0; b < nb; ++b)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) t[b * n * n + (size_t)j * n + i] = S[b * n * n + (size_t)i * n + j];
+    return t;
   };
   d.dim = h.dim;
   d.P = h.P;
@@ -304,20 +357,12 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, std::vector<std
     dd.ecoef = put(s.ecoef);
     dd.nbr = put_int(s.nbr);
     if (!s.S_ec.empty()) {
-      auto transp = [](const std::vector<double>& S, int n) {
-        std::vector<double> t(S.size());
-        const size_t nb = S.size() / ((size_t)n * n);
-        for (size_t b = 0; b < nb; ++b)
-          for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) t[b * n * n + (size_t)j * n + i] = S[b * n * n + (size_t)i * n + j];
-        return t;
-      };
-      dd.ST_ec = put(transp(s.S_ec, s.n_ec));
-      dd.ST_fc = put(transp(s.S_fc, s.n_fc));
       dd.S_ec = put(s.S_ec);
+      dd.ST_ec = put(transp(s.S_ec, s.n_ec));
       dd.lam_ec = put(s.lam_ec);
       dd.w_ec = put(s.w_ec);
       dd.S_fc = put(s.S_fc);
+      dd.ST_fc = put(transp(s.S_fc, s.n_fc));
       dd.lam_fc = put(s.lam_fc);
       dd.w_fc = put(s.w_fc);
     }
@@ -336,7 +381,7 @@ size_t sweep_patch_elems(const LevelHost& lv, int nd) {
   return np * ts;
 }
 
-int layout(dgmg_handle* h, char* base, std::vector<std::pair<void*, std::vector<char>>>* up) {
+void layout(dgmg_handle* h, char* base, Upload* up) {
   Carver cv{base};
   const int nl = (int)h->lv.size();
   h->Ld.assign(nl, LevelDev<double>());
@@ -345,7 +390,6 @@ int layout(dgmg_handle* h, char* base, std::vector<std::pair<void*, std::vector<
     carve_level<double>(cv, h->lv[l], h->Ld[l], up);
     carve_level<float>(cv, h->lv[l], h->Lf[l], up);
   }
-  // coarse global eigenpairs
   const LevelHost& l0 = h->lv[0];
   h->cdev.dim = l0.dim;
   for (int d = 0; d < 3; ++d) {
@@ -390,11 +434,15 @@ int layout(dgmg_handle* h, char* base, std::vector<std::pair<void*, std::vector<
   h->pp = (double*)cv.take(nt * 8);
   h->pq = (double*)cv.take(nt * 8);
   h->pz = (double*)cv.take(nt * 8);
-  const size_t apply_blocks = h->lv.back().n_elem + 8;
-  h->part = (double*)cv.take(std::max<size_t>(2 * RED_BLOCKS, apply_blocks) * 8 + 2 * RED_BLOCKS * 8);
+  const size_t np1 = std::max<size_t>(RED_BLOCKS, h->lv.back().n_elem + 8);
+  h->part = (double*)cv.take(np1 * 8);
+  h->part2 = (double*)cv.take(RED_BLOCKS * 8);
   h->scal = (double*)cv.take(64 * 8);
   h->ws_need = cv.off + 256;
-  return DGMG_OK;
+  for (int l = 0; l < nl; ++l) {
+    h->Ld[l].active = h->active;
+    h->Lf[l].active = h->active;
+  }
 }
 
 // ---------------------------------------------------------------- typed level operations
@@ -414,17 +462,34 @@ int k_apply(dgmg_handle* h, int l, int mode, const T* x, const T* f, T* y, doubl
   return check_hip(h, "apply");
 }
 
+void sweep_shape(const LevelHost& lv, int nd, int np[3], int& NA, int& NL) {
+  np[0] = np[1] = np[2] = 1;
+  for (int d = 0; d < lv.dim; ++d) np[d] = (d == nd) ? lv.dir[d].nf : lv.dir[d].N;
+  NL = lv.NP + 2 * lv.NO;
+  NA = nd < 0 ? NL : 2 * lv.P;
+}
+
+template <class T>
+int k_fdm(dgmg_handle* h, int l, int nd, const T* r, int waves) {
+  const LevelDev<T>& L = LD<T>(h, l);
+  int np[3], NA, NL;
+  sweep_shape(h->lv[l], nd, np, NA, NL);
+  T* pb = (T*)h->patch;
+  int rc = L.dim == 3 ? Kern<T, 3>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, h->stream)
+                      : Kern<T, 2>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, h->stream);
+  if (rc) return fail(h, DGMG_EUNSUPPORTED, "no patch-solve kernel for this tile");
+  return DGMG_OK;
+}
+
 template <class T>
 int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r) {
   const LevelDev<T>& L = LD<T>(h, l);
   const LevelHost& lv = h->lv[l];
   int rc = k_apply<T>(h, l, 1, u, f, r, nullptr, nullptr);
   if (rc) return rc;
-  int np[3] = {1, 1, 1};
-  for (int d = 0; d < lv.dim; ++d) np[d] = (d == nd) ? lv.dir[d].nf : lv.dir[d].N;
-  const int NL = lv.NP + 2 * lv.NO;
-  const int NA = nd < 0 ? NL : 2 * lv.P;
-  T* pb = (T*)h->patch;
+  int np[3], NA, NL;
+  sweep_shape(lv, nd, np, NA, NL);
+  const int kind = nd < 0 ? 3 : nd;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = h->timing && l == (int)h->lv.size() - 1;  // top-level launches only
   if (timed) {
@@ -432,24 +497,24 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r) {
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, h->stream);
   }
-  rc = L.dim == 3 ? Kern<T, 3>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], h->stream)
-                  : Kern<T, 2>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], h->stream);
-  if (rc) return fail(h, DGMG_EUNSUPPORTED, "no patch-solve kernel for this tile");
+  rc = k_fdm<T>(h, l, nd, r, h->waves[l][kind]);
+  if (rc) return rc;
   if (timed) {
     (void)hipEventRecord(e1, h->stream);
     h->ev.emplace_back(e0, e1);
-    // algorithmic cost of one launch: 2 flops per multiply-add of the 2D
-    // forward and backward 1D contractions, plus scale and weight; bytes:
-    // residual read + weighted correction written, per patch tile
-    double npatch = (double)np[0] * np[1] * np[2];
-    double ts = NA, fl = 0.0;
+    // algorithmic cost of one launch: 2 flops per multiply-add of the forward
+    // and backward 1D contractions plus the scale and the weight; bytes: the
+    // residual tile read and the weighted correction written, per patch
+    const double npatch = (double)np[0] * np[1] * np[2];
+    double ts = NA;
     for (int d = 1; d < lv.dim; ++d) ts *= NL;
-    fl = 2.0 * 2.0 * ts * (NA + (lv.dim - 1) * NL) + 2.0 * ts;
+    const double fl = 2.0 * 2.0 * ts * (NA + (lv.dim - 1) * NL) + 2.0 * ts;
     h->ev_flops.push_back(npatch * fl);
     h->ev_bytes.push_back(npatch * ts * 2.0 * sizeof(T));
   }
   rc = check_hip(h, "patch solve");
   if (rc) return rc;
+  T* pb = (T*)h->patch;
   rc = L.dim == 3 ? Kern<T, 3>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], h->stream)
                   : Kern<T, 2>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no combine kernel for this order");
@@ -482,8 +547,17 @@ int k_transfer(dgmg_handle* h, int l, bool restr, const T* in, T* out) {
 }
 
 template <class T>
-void k_fill_v(dgmg_handle* h, T* a, int64_t n) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, T(0), n);
+void k_fill_v(dgmg_handle* h, T* a, int64_t n, T v = T(0)) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, v, n, h->active);
+}
+
+// sum of a (n doubles) into *out, using c_a as a vector of ones
+void k_mean_sub(dgmg_handle* h, double* a, int64_t n) {
+  k_fill_v<double>(h, h->c_a, n, 1.0);
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, a, h->c_a, n, h->part, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 41, h->active);
+  hipLaunchKernelGGL(k_sub_scalar, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, h->scal + 41,
+                     1.0 / (double)n, n, h->active);
 }
 
 // u0 = A0^+ f0 (double vectors) by global fast diagonalisation.
@@ -496,40 +570,29 @@ int coarse_fdm(dgmg_handle* h, const double* f0, double* u0) {
   bool periodic_all = true;
   for (int d = 0; d < dim; ++d) periodic_all = periodic_all && l0.dir[d].periodic;
   if (periodic_all) {  // make f0 orthogonal to the constants (Euclidean mean)
-    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, f0, h->c_f, n);
-    hipLaunchKernelGGL(k_fill<double>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, h->c_a, 1.0, n);
-    hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->c_f, h->c_a, n, h->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 41);
-    hipLaunchKernelGGL(k_sub_scalar, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, h->c_f, h->scal + 41, 1.0 / (double)n, n);
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, f0, h->c_f, n, h->active);
+    k_mean_sub(h, h->c_f, n);
     src = h->c_f;
   }
-  double* a = h->c_a;
-  double* b = h->c_b;
-  // forward passes x, y, (z with scale)
+  double* bufs[2] = {h->c_a, h->c_b};
   const double* in = src;
-  double* bufs[2] = {a, b};
   int k = 0;
   for (int d = 0; d < dim; ++d) {
     double* out = bufs[k];
     if (d == dim - 1)
-      hipLaunchKernelGGL((k_coarse_pass<true, true>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n);
+      hipLaunchKernelGGL((k_coarse_pass<true, true>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
     else
-      hipLaunchKernelGGL((k_coarse_pass<true, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n);
+      hipLaunchKernelGGL((k_coarse_pass<true, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
     in = out;
     k ^= 1;
   }
   for (int d = dim - 1; d >= 0; --d) {
     double* out = d == 0 ? u0 : bufs[k];
-    hipLaunchKernelGGL((k_coarse_pass<false, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n);
+    hipLaunchKernelGGL((k_coarse_pass<false, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
     in = out;
     k ^= 1;
   }
-  if (periodic_all) {  // mean-free (minimum-norm) representative
-    hipLaunchKernelGGL(k_fill<double>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, h->c_a, 1.0, n);
-    hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, u0, h->c_a, n, h->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 41);
-    hipLaunchKernelGGL(k_sub_scalar, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, u0, h->scal + 41, 1.0 / (double)n, n);
-  }
+  if (periodic_all) k_mean_sub(h, u0, n);  // mean-free (minimum-norm) representative
   return check_hip(h, "coarse solve");
 }
 
@@ -540,18 +603,18 @@ int k_coarse<double>(dgmg_handle* h, const double* f0, double* u0) { return coar
 template <>
 int k_coarse<float>(dgmg_handle* h, const float* f0, float* u0) {
   const int64_t n = h->lv[0].n_dof;
-  // FP64 copies: input in the level-0 residual buffer (sized for doubles),
-  // result in the patch buffer (c_a, c_b and c_f are used by coarse_fdm)
+  // FP64 copies: input in the level-0 residual buffer (sized for doubles), result
+  // in the patch buffer (c_a, c_b and c_f are used by coarse_fdm)
   double* tmp_in = (double*)h->buf[0].r;
   double* res = (double*)h->patch;
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, f0, tmp_in, n);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, f0, tmp_in, n, h->active);
   int rc = coarse_fdm(h, tmp_in, res);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, res, u0, n);
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, res, u0, n, h->active);
   return check_hip(h, "coarse convert");
 }
 
-// z = MultigridCycle(0, r) on MG-precision vectors (Alg. 1).
+// z = MultigridCycle(0, r) on multigrid-precision vectors (Alg. 1).
 template <class T>
 int k_vcycle(dgmg_handle* h, const T* r, T* z) {
   const int L = (int)h->lv.size() - 1;
@@ -564,7 +627,7 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
   f[L] = const_cast<T*>(r);
   const bool var = h->opts.vcycle == DGMG_VCYCLE_VARIABLE;
   auto ns = [&](int l, int which) {
-    int base = which == 0 ? h->opts.ns_pre : h->opts.ns_post;
+    const int base = which == 0 ? h->opts.ns_pre : h->opts.ns_post;
     return var ? base << (L - l) : base;
   };
   k_fill_v<T>(h, u[L], h->lv[L].n_dof);
@@ -596,11 +659,136 @@ int precond(dgmg_handle* h, const double* r, double* z) {
   if (!mixed(h)) return k_vcycle<double>(h, r, z);
   float* rf = (float*)h->buf[L].f;
   float* zf = (float*)h->buf[L].u;
-  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, r, rf, n);
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, r, rf, n, h->active);
   int rc = k_vcycle<float>(h, rf, zf);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, zf, z, n);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, zf, z, n, h->active);
   return check_hip(h, "precond convert");
+}
+
+// ---------------------------------------------------------------- MGCG phases (Alg. 2)
+// Fixed device scalar slots so that a phase can be captured once and replayed.
+enum { S_DELTA = 0, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5 };
+
+double* rr_slot(dgmg_handle* h) { return h->rr_out ? h->rr_out : h->scal + S_RR; }
+
+// r = g - A x; r_old = 0; r.r
+int pcg_init_a(dgmg_handle* h, const double* rhs, const double* x) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  int rc = k_apply<double>(h, L, 1, x, rhs, h->pr, nullptr, nullptr);
+  if (rc) return rc;
+  k_fill_v<double>(h, h->pro, n);
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pr, h->pr, n, h->part, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, rr_slot(h), h->active);
+  return check_hip(h, "pcg init");
+}
+
+// p = MG(r); delta = p.r
+int pcg_init_b(dgmg_handle* h) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  int rc = precond(h, h->pr, h->pp);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, h->pr, n, h->part, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + S_DELTA, h->active);
+  return check_hip(h, "pcg init");
+}
+
+// q = A p; alpha = delta / p.q; x += alpha p; r -= alpha q; r.r
+int pcg_phase_a(dgmg_handle* h, double* x) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  int nb = 0;
+  int rc = k_apply<double>(h, L, 2, h->pp, nullptr, h->pq, h->part, &nb);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, nb, h->scal + S_PQ, h->active);
+  hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, h->pr, h->pp, h->pq,
+                     h->scal + S_DELTA, h->scal + S_PQ, n, h->part2, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, rr_slot(h), h->active);
+  return check_hip(h, "pcg phase a");
+}
+
+// z = MG(r); beta = z.(r - r_old) / delta; p = z + beta p; r_old = r; delta = z.r
+int pcg_phase_b(dgmg_handle* h) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  int rc = precond(h, h->pr, h->pz);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_dot_zr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro, n,
+                     h->part, h->part2, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + S_ZDR, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, h->scal + S_ZR, h->active);
+  hipLaunchKernelGGL(k_update_p, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, h->pz, h->pr, h->pro,
+                     h->scal + S_ZDR, h->scal + S_DELTA, n, h->active);
+  hipLaunchKernelGGL(k_copy, dim3(1), dim3(64), 0, h->stream, h->scal + S_ZR, h->scal + S_DELTA, (int64_t)1, h->active);
+  return check_hip(h, "pcg phase b");
+}
+
+// Record `fn` into a graph.  The capture runs on a private non-blocking stream
+// (the caller's stream may be the legacy default stream, which cannot be
+// captured); the graph is later launched on the caller's stream.
+template <class F>
+int capture(dgmg_handle* h, hipGraph_t* g, F fn) {
+  if (!h->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("capture stream: ") + hipGetErrorString(e));
+  }
+  const bool t = h->timing;
+  hipStream_t user = h->stream;
+  h->timing = false;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    h->timing = t;
+    return fail(h, DGMG_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+  }
+  h->stream = h->cap_stream;
+  int rc = fn();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(h->cap_stream, &graph);
+  h->stream = user;
+  h->timing = t;
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("end capture: ") + hipGetErrorString(e));
+  *g = graph;
+  return DGMG_OK;
+}
+
+void drop_graphs(dgmg_handle* h) {
+  for (auto& g : h->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  h->graph_x = nullptr;
+}
+
+int instantiate(dgmg_handle* h, hipGraph_t g, hipGraphExec_t* ex) {
+  hipError_t e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return DGMG_OK;
+}
+
+int run_phase(dgmg_handle* h, int which, double* x) {
+  if (!h->use_graphs) return which == 0 ? pcg_phase_a(h, x) : pcg_phase_b(h);
+  if (which == 0 && h->gexec[0] && h->graph_x != x) {
+    (void)hipGraphExecDestroy(h->gexec[0]);
+    h->gexec[0] = nullptr;
+  }
+  if (!h->gexec[which]) {
+    hipGraph_t g = nullptr;
+    int rc = capture(h, &g, [&]() { return which == 0 ? pcg_phase_a(h, x) : pcg_phase_b(h); });
+    if (rc) return rc;
+    if ((rc = instantiate(h, g, &h->gexec[which]))) return rc;
+    if (which == 0) h->graph_x = x;
+  }
+  hipError_t e = hipGraphLaunch(h->gexec[which], h->stream);
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+  return DGMG_OK;
 }
 
 int read_scalar(dgmg_handle* h, const double* dev, double* out) {
@@ -620,6 +808,98 @@ int need_bound(dgmg_handle* h) {
 int check_level(dgmg_handle* h, int level, int minl = 0) {
   if (level < minl || level >= (int)h->lv.size()) return fail(h, DGMG_EINVAL, "level out of range");
   return DGMG_OK;
+}
+
+int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
+  if (!g || !o) return fail(nullptr, DGMG_EINVAL, "null argument");
+  if (g->dim != 2 && g->dim != 3) return fail(nullptr, DGMG_EINVAL, "dim must be 2 or 3");
+  const int okP[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  if (std::find(std::begin(okP), std::end(okP), o->P) == std::end(okP))
+    return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16");
+  if (!(o->mu_star > 0) || !std::isfinite(o->mu_star)) return fail(nullptr, DGMG_EINVAL, "mu_star must be > 0");
+  if (o->flux != DGMG_FLUX_IP && o->flux != DGMG_FLUX_LDG) return fail(nullptr, DGMG_EINVAL, "bad flux");
+  if (o->smoother != DGMG_SMOOTHER_EA && o->smoother != DGMG_SMOOTHER_FA) return fail(nullptr, DGMG_EINVAL, "bad smoother");
+  if (o->weighting < 0 || o->weighting > 3) return fail(nullptr, DGMG_EINVAL, "bad weighting");
+  if (o->vcycle != DGMG_VCYCLE_CLASSICAL && o->vcycle != DGMG_VCYCLE_VARIABLE) return fail(nullptr, DGMG_EINVAL, "bad vcycle");
+  if (o->precision != DGMG_PREC_FP64 && o->precision != DGMG_PREC_MIXED) return fail(nullptr, DGMG_EINVAL, "bad precision");
+  if (o->ns_pre < 0 || o->ns_post < 0 || o->max_iter < 0) return fail(nullptr, DGMG_EINVAL, "negative count");
+  if (o->overlap < -2) return fail(nullptr, DGMG_EINVAL, "bad overlap");
+  sp = SetupParams();
+  sp.dim = g->dim;
+  for (int d = 0; d < g->dim; ++d) {
+    if (g->n_elem[d] < 1 || !g->dx[d]) return fail(nullptr, DGMG_EINVAL, "n_elem < 1 or dx missing");
+    if (g->periodic[d] && g->n_elem[d] < 3) return fail(nullptr, DGMG_EINVAL, "periodic direction needs >= 3 elements");
+    sp.n[d] = g->n_elem[d];
+    sp.periodic[d] = g->periodic[d] != 0;
+    sp.dx[d].assign(g->dx[d], g->dx[d] + g->n_elem[d]);
+    for (double v : sp.dx[d])
+      if (!(v > 0) || !std::isfinite(v)) return fail(nullptr, DGMG_EINVAL, "dx must be finite and > 0");
+    if (o->flux == DGMG_FLUX_LDG && !(std::fabs(o->beta[d]) <= 1.0)) return fail(nullptr, DGMG_EINVAL, "|beta| must be <= 1");
+  }
+  int64_t ne = 1;
+  for (int d = 0; d < g->dim; ++d) ne *= g->n_elem[d];
+  if (ne * (int64_t)std::pow(o->P + 1, g->dim) > (int64_t)INT32_MAX * 4) return fail(nullptr, DGMG_EINVAL, "problem too large");
+  sp.P = o->P;
+  sp.flux = o->flux;
+  for (int d = 0; d < 3; ++d) sp.beta[d] = o->beta[d];
+  sp.mu_star = o->mu_star;
+  sp.smoother = o->smoother;
+  sp.overlap = o->overlap;
+  sp.weighting = o->weighting;
+  return DGMG_OK;
+}
+
+// Time the patch-solve block shapes of every sweep and keep the fastest.
+template <class T>
+int autotune_t(dgmg_handle* h) {
+  const int nl = (int)h->lv.size();
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int rc = DGMG_OK;
+  for (int l = 1; l < nl && !rc; ++l) {
+    T* r = (T*)h->buf[l].r;
+    k_fill_v<T>(h, r, h->lv[l].n_dof);
+    const int nkinds = h->opts.smoother == DGMG_SMOOTHER_EA ? 1 : h->lv[l].dim;
+    for (int q = 0; q < nkinds && !rc; ++q) {
+      const int nd = h->opts.smoother == DGMG_SMOOTHER_EA ? -1 : q;
+      const int kind = nd < 0 ? 3 : nd;
+      float best = 1e30f;
+      int bw = 0;
+      for (int w : {1, 2, 4}) {
+        if ((rc = k_fdm<T>(h, l, nd, r, w))) break;
+        (void)hipEventRecord(e0, h->stream);
+        for (int rep = 0; rep < 3; ++rep)
+          if ((rc = k_fdm<T>(h, l, nd, r, w))) break;
+        (void)hipEventRecord(e1, h->stream);
+        if (rc) break;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+          rc = fail(h, DGMG_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          bw = w;
+        }
+      }
+      h->waves[l][kind] = bw;
+      h->tune_ms[l][kind] = best / 3.0f;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc) rc = check_hip(h, "autotune");
+  drop_graphs(h);
+  return rc;
+}
+
+int bind_batch_member(dgmg_handle* h, char* dev, hipStream_t s, const int* flag, double* rr) {
+  h->active = flag;
+  h->rr_out = rr;
+  return dgmg_bind_workspace(h, dev, h->ws_need, s);
 }
 
 }  // namespace
@@ -645,43 +925,11 @@ int dgmg_opts_default(dgmg_opts* o) {
 }
 
 int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out) {
-  if (!g || !o || !out) return fail(nullptr, DGMG_EINVAL, "null argument");
+  if (!out) return fail(nullptr, DGMG_EINVAL, "null argument");
   *out = nullptr;
-  if (g->dim != 2 && g->dim != 3) return fail(nullptr, DGMG_EINVAL, "dim must be 2 or 3");
-  const int okP[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  if (std::find(std::begin(okP), std::end(okP), o->P) == std::end(okP))
-    return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16");
-  if (!(o->mu_star > 0) || !std::isfinite(o->mu_star)) return fail(nullptr, DGMG_EINVAL, "mu_star must be > 0");
-  if (o->flux != DGMG_FLUX_IP && o->flux != DGMG_FLUX_LDG) return fail(nullptr, DGMG_EINVAL, "bad flux");
-  if (o->smoother != DGMG_SMOOTHER_EA && o->smoother != DGMG_SMOOTHER_FA) return fail(nullptr, DGMG_EINVAL, "bad smoother");
-  if (o->weighting < 0 || o->weighting > 3) return fail(nullptr, DGMG_EINVAL, "bad weighting");
-  if (o->vcycle != DGMG_VCYCLE_CLASSICAL && o->vcycle != DGMG_VCYCLE_VARIABLE) return fail(nullptr, DGMG_EINVAL, "bad vcycle");
-  if (o->precision != DGMG_PREC_FP64 && o->precision != DGMG_PREC_MIXED) return fail(nullptr, DGMG_EINVAL, "bad precision");
-  if (o->ns_pre < 0 || o->ns_post < 0 || o->max_iter < 0) return fail(nullptr, DGMG_EINVAL, "negative count");
-  if (o->overlap < -2) return fail(nullptr, DGMG_EINVAL, "bad overlap");
   SetupParams sp;
-  sp.dim = g->dim;
-  for (int d = 0; d < g->dim; ++d) {
-    if (g->n_elem[d] < 1 || !g->dx[d]) return fail(nullptr, DGMG_EINVAL, "n_elem < 1 or dx missing");
-    if (g->periodic[d] && g->n_elem[d] < 3) return fail(nullptr, DGMG_EINVAL, "periodic direction needs >= 3 elements");
-    sp.n[d] = g->n_elem[d];
-    sp.periodic[d] = g->periodic[d] != 0;
-    sp.dx[d].assign(g->dx[d], g->dx[d] + g->n_elem[d]);
-    for (double v : sp.dx[d])
-      if (!(v > 0) || !std::isfinite(v)) return fail(nullptr, DGMG_EINVAL, "dx must be finite and > 0");
-    if (o->flux == DGMG_FLUX_LDG && !(std::fabs(o->beta[d]) <= 1.0)) return fail(nullptr, DGMG_EINVAL, "|beta| must be <= 1");
-  }
-  int64_t ne = 1;
-  for (int d = 0; d < g->dim; ++d) ne *= g->n_elem[d];
-  if (ne * (int64_t)std::pow(o->P + 1, g->dim) > (int64_t)INT32_MAX * 4)
-    return fail(nullptr, DGMG_EINVAL, "problem too large");
-  sp.P = o->P;
-  sp.flux = o->flux;
-  for (int d = 0; d < 3; ++d) sp.beta[d] = o->beta[d];
-  sp.mu_star = o->mu_star;
-  sp.smoother = o->smoother;
-  sp.overlap = o->overlap;
-  sp.weighting = o->weighting;
+  int rc = validate_setup(g, o, sp);
+  if (rc) return rc;
   dgmg_handle* h = new dgmg_handle();
   h->sp = sp;
   h->opts = *o;
@@ -690,16 +938,19 @@ int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out) {
     delete h;
     return fail(nullptr, DGMG_EINVAL, e);
   }
-  // kernels must exist for every smoothing level
-  for (size_t l = 1; l < h->lv.size(); ++l) {
+  if ((int)h->lv.size() > MAXL) {
+    delete h;
+    return fail(nullptr, DGMG_EUNSUPPORTED, "too many levels");
+  }
+  for (size_t l = 1; l < h->lv.size(); ++l) {  // kernels must exist for every smoothing level
     const LevelHost& lv = h->lv[l];
     const int NL = lv.NP + 2 * lv.NO;
-    bool ok = o->smoother == DGMG_SMOOTHER_EA
-                  ? (g->dim == 3 ? Kern<double, 3>::fdm_supported(NL, NL) : Kern<double, 2>::fdm_supported(NL, NL))
-                  : (g->dim == 3 ? Kern<double, 3>::fdm_supported(2 * lv.P, NL) : Kern<double, 2>::fdm_supported(2 * lv.P, NL));
+    const int NA = o->smoother == DGMG_SMOOTHER_EA ? NL : 2 * lv.P;
+    const bool ok = g->dim == 3 ? Kern<double, 3>::fdm_supported(NA, NL) : Kern<double, 2>::fdm_supported(NA, NL);
     if (!ok) {
       delete h;
-      return fail(nullptr, DGMG_EUNSUPPORTED, "no patch kernel for P_l=" + std::to_string(lv.P) + " N_O=" + std::to_string(lv.NO));
+      return fail(nullptr, DGMG_EUNSUPPORTED,
+                  "no patch kernel for P_l=" + std::to_string(lv.P) + " N_O=" + std::to_string(lv.NO));
     }
   }
   layout(h, nullptr, nullptr);
@@ -717,10 +968,11 @@ int dgmg_bind_workspace(dgmg_handle* h, void* dev, size_t bytes, void* stream) {
   if (!h || !dev) return DGMG_EINVAL;
   if (bytes < h->ws_need) return fail(h, DGMG_ENOMEM, "workspace too small");
   if (((uintptr_t)dev) & 255) return fail(h, DGMG_EINVAL, "workspace must be 256-byte aligned");
+  drop_graphs(h);
   h->stream = (hipStream_t)stream;
   h->ws = (char*)dev;
   h->ws_bytes = bytes;
-  std::vector<std::pair<void*, std::vector<char>>> up;
+  Upload up;
   layout(h, h->ws, &up);
   for (auto& u : up) {
     hipError_t e = hipMemcpyAsync(u.first, u.second.data(), u.second.size(), hipMemcpyHostToDevice, h->stream);
@@ -738,7 +990,15 @@ int dgmg_bind_workspace(dgmg_handle* h, void* dev, size_t bytes, void* stream) {
 
 int dgmg_set_stream(dgmg_handle* h, void* stream) {
   if (!h) return DGMG_EINVAL;
+  if (h->stream != (hipStream_t)stream) drop_graphs(h);
   h->stream = (hipStream_t)stream;
+  return DGMG_OK;
+}
+
+int dgmg_use_graphs(dgmg_handle* h, int enable) {
+  if (!h) return DGMG_EINVAL;
+  drop_graphs(h);
+  h->use_graphs = enable != 0;
   return DGMG_OK;
 }
 
@@ -833,26 +1093,11 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
   int rc = need_bound(h);
   if (rc) return rc;
   if (!rhs || !x || !(tol >= 0)) return fail(h, DGMG_EINVAL, "bad arguments");
-  const int L = (int)h->lv.size() - 1;
-  const int64_t n = h->lv[L].n_dof;
-  double* r = h->pr;
-  double* ro = h->pro;
-  double* p = h->pp;
-  double* q = h->pq;
-  double* z = h->pz;
-  double* part1 = h->part;
-  double* part2 = h->part + std::max<size_t>(2 * RED_BLOCKS, h->lv.back().n_elem + 8);
-  double* S = h->scal;  // slots: 0,1 delta (alternating), 2 pq, 3 rr, 4 zdr, 5 zr
-  const dim3 vb(RED_BLOCKS), vt(VEC_THREADS);
+  if (h->active) return fail(h, DGMG_EINVAL, "handle belongs to a batch");
   if (st) std::memset(st, 0, sizeof(*st));
-  // r = g - A x ; r_old = 0
-  rc = k_apply<double>(h, L, 1, x, rhs, r, nullptr, nullptr);
-  if (rc) return rc;
-  k_fill_v<double>(h, ro, n);
-  hipLaunchKernelGGL(k_dot, vb, vt, 0, h->stream, r, r, n, part1);
-  hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part1, RED_BLOCKS, S + 3);
+  if ((rc = pcg_init_a(h, rhs, x))) return rc;
   double rr;
-  if ((rc = read_scalar(h, S + 3, &rr))) return rc;
+  if ((rc = read_scalar(h, rr_slot(h), &rr))) return rc;
   const double r0 = std::sqrt(rr);
   if (!std::isfinite(r0)) return fail(h, DGMG_ENONFINITE, "initial residual is not finite");
   if (st) {
@@ -863,23 +1108,11 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
   }
   if (r0 == 0.0) return DGMG_OK;
   const double rmax = tol * r0;
-  // p = MG(r); delta = p.r
-  if ((rc = precond(h, r, p))) return rc;
-  hipLaunchKernelGGL(k_dot, vb, vt, 0, h->stream, p, r, n, part1);
-  hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part1, RED_BLOCKS, S + 0);
-  int cur = 0;
-  int it = 0;
+  if ((rc = pcg_init_b(h))) return rc;
   double rn = r0;
-  for (it = 1; it <= h->opts.max_iter; ++it) {
-    int nb = 0;
-    // q = A p, partial p.q
-    rc = k_apply<double>(h, L, 2, p, nullptr, q, part1, &nb);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part1, nb, S + 2);
-    hipLaunchKernelGGL(k_update_xr, vb, vt, 0, h->stream, x, r, p, q, S + cur, S + 2, n, part2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part2, RED_BLOCKS, S + 3);
-    if ((rc = check_hip(h, "pcg update"))) return rc;
-    if ((rc = read_scalar(h, S + 3, &rr))) return rc;
+  for (int it = 1; it <= h->opts.max_iter; ++it) {
+    if ((rc = run_phase(h, 0, x))) return rc;
+    if ((rc = read_scalar(h, rr_slot(h), &rr))) return rc;
     rn = std::sqrt(rr);
     if (st) {
       st->iterations = it;
@@ -888,12 +1121,7 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
     }
     if (!std::isfinite(rn)) return fail(h, DGMG_ENONFINITE, "residual norm is not finite");
     if (rn <= rmax) break;
-    if ((rc = precond(h, r, z))) return rc;
-    hipLaunchKernelGGL(k_dot_zr, vb, vt, 0, h->stream, z, r, ro, n, part1, part2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part1, RED_BLOCKS, S + 4);
-    hipLaunchKernelGGL(k_finalize, dim3(1), vt, 0, h->stream, part2, RED_BLOCKS, S + (cur ^ 1));
-    hipLaunchKernelGGL(k_update_p, vb, vt, 0, h->stream, p, z, r, ro, S + 4, S + cur, n);
-    cur ^= 1;
+    if ((rc = run_phase(h, 1, nullptr))) return rc;
   }
   if ((rc = check_hip(h, "pcg"))) return rc;
   const bool conv = rn <= rmax;
@@ -902,6 +1130,27 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
     if (st->iterations > 0) st->rho = std::pow(rn / r0, 1.0 / st->iterations);
   }
   return conv ? DGMG_OK : DGMG_NOT_CONVERGED;
+}
+
+int dgmg_autotune(dgmg_handle* h) {
+  int rc = need_bound(h);
+  if (rc) return rc;
+  return mixed(h) ? autotune_t<float>(h) : autotune_t<double>(h);
+}
+
+int dgmg_tune_get(const dgmg_handle* h, int level, int kind, int* waves, double* ms) {
+  if (!h || level < 1 || level >= (int)h->lv.size() || kind < 0 || kind >= NKIND) return DGMG_EINVAL;
+  if (waves) *waves = h->waves[level][kind];
+  if (ms) *ms = h->tune_ms[level][kind];
+  return DGMG_OK;
+}
+
+int dgmg_tune_set(dgmg_handle* h, int level, int kind, int waves) {
+  if (!h || level < 1 || level >= (int)h->lv.size() || kind < 0 || kind >= NKIND || waves < 0 || waves > 4)
+    return DGMG_EINVAL;
+  h->waves[level][kind] = waves;
+  drop_graphs(h);
+  return DGMG_OK;
 }
 
 int dgmg_kernel_timing(dgmg_handle* h, int enable) {
@@ -946,12 +1195,343 @@ int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double
 void dgmg_destroy(dgmg_handle* h) {
   if (!h) return;
   dgmg_kernel_timing(h, 0);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   delete h;
 }
 
-const char* dgmg_last_error(const dgmg_handle* h) {
-  return h ? h->err.c_str() : g_setup_error.c_str();
+const char* dgmg_last_error(const dgmg_handle* h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
+
+// ------------------------------------------------------------------- batches
+int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, dgmg_batch** out) {
+  if (!out || count < 1 || !grids || !opts) return fail(nullptr, DGMG_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  dgmg_batch* b = new dgmg_batch();
+  Carver cv{nullptr};
+  cv.take(count * sizeof(int));
+  cv.take(count * sizeof(double));
+  b->dof_off.push_back(0);
+  for (int i = 0; i < count; ++i) {
+    dgmg_handle* h = nullptr;
+    int rc = dgmg_setup(&grids[i], &opts[i], &h);
+    if (rc) {
+      for (auto* x : b->h) dgmg_destroy(x);
+      delete b;
+      g_setup_error = "grid " + std::to_string(i) + ": " + g_setup_error;
+      return rc;
+    }
+    b->h.push_back(h);
+    cv.off = (cv.off + 255) & ~size_t(255);  // member workspaces: 256-aligned, disjoint
+    b->sub_off.push_back(cv.off);
+    cv.off += h->ws_need;
+    b->dof_off.push_back(b->dof_off.back() + h->lv.back().n_dof);
+  }
+  b->ws_need = cv.off + 256;
+  *out = b;
+  return DGMG_OK;
+}
+
+int dgmg_batch_workspace_bytes(const dgmg_batch* b, size_t* bytes) {
+  if (!b || !bytes) return DGMG_EINVAL;
+  *bytes = b->ws_need;
+  return DGMG_OK;
+}
+
+int dgmg_batch_offsets(const dgmg_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return DGMG_EINVAL;
+  for (size_t i = 0; i < b->dof_off.size(); ++i) offsets[i] = b->dof_off[i];
+  return DGMG_OK;
+}
+
+int dgmg_batch_handle(dgmg_batch* b, int i, dgmg_handle** h) {
+  if (!b || !h || i < 0 || i >= (int)b->h.size()) return DGMG_EINVAL;
+  *h = b->h[i];
+  return DGMG_OK;
+}
+
+int dgmg_batch_bind_workspace(dgmg_batch* b, void* dev, size_t bytes, void* stream) {
+  if (!b || !dev) return DGMG_EINVAL;
+  if (bytes < b->ws_need) {
+    b->err = "workspace too small";
+    return DGMG_ENOMEM;
+  }
+  if (((uintptr_t)dev) & 255) {
+    b->err = "workspace must be 256-byte aligned";
+    return DGMG_EINVAL;
+  }
+  for (auto& g : b->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  b->stream = (hipStream_t)stream;
+  b->ws = (char*)dev;
+  const int n = (int)b->h.size();
+  Carver cv{b->ws};
+  b->flags_dev = (int*)cv.take(n * sizeof(int));
+  b->rr_dev = (double*)cv.take(n * sizeof(double));
+  if (!b->flags_host) {
+    if (hipHostMalloc((void**)&b->flags_host, n * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->rr_host, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      b->err = "pinned alloc failed";
+      return DGMG_EHIP;
+    }
+  }
+  // every member range must lie after the header, be aligned and end before the next one
+  size_t prev_end = cv.off;
+  for (int i = 0; i < n; ++i) {
+    const size_t lo = b->sub_off[i], hi = lo + b->h[i]->ws_need;
+    if (lo < prev_end || (lo & 255) || hi > b->ws_need) {
+      b->err = "internal: batch workspace layout is inconsistent";
+      return DGMG_EINVAL;
+    }
+    prev_end = hi;
+  }
+  for (int i = 0; i < n; ++i) {
+    int rc = bind_batch_member(b->h[i], b->ws + b->sub_off[i], b->stream, b->flags_dev + i, b->rr_dev + i);
+    if (rc) {
+      b->err = "grid " + std::to_string(i) + ": " + b->h[i]->err;
+      return rc;
+    }
+  }
+  b->bound = true;
+  return DGMG_OK;
+}
+
+static int batch_fail(dgmg_batch* b, int code, const std::string& msg) {
+  b->err = msg;
+  return code;
+}
+
+static int batch_flags_upload(dgmg_batch* b) {
+  hipError_t e = hipMemcpyAsync(b->flags_dev, b->flags_host, b->h.size() * sizeof(int), hipMemcpyHostToDevice,
+                                b->stream);
+  return e == hipSuccess ? DGMG_OK : batch_fail(b, DGMG_EHIP, std::string("flag upload: ") + hipGetErrorString(e));
+}
+
+static int batch_rr_download(dgmg_batch* b) {
+  hipError_t e = hipMemcpyAsync(b->rr_host, b->rr_dev, b->h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? DGMG_OK : batch_fail(b, DGMG_EHIP, std::string("norm readback: ") + hipGetErrorString(e));
+}
+
+int dgmg_batch_autotune(dgmg_batch* b) {
+  if (!b || !b->bound) return DGMG_EINVAL;
+  for (size_t i = 0; i < b->h.size(); ++i) b->flags_host[i] = 1;
+  int rc = batch_flags_upload(b);
+  if (rc) return rc;
+  // grids whose sweeps have the same tile and patch counts share one measurement
+  std::vector<std::pair<std::vector<int64_t>, int>> seen;
+  for (dgmg_handle* h : b->h) {
+    for (int l = 1; l < (int)h->lv.size(); ++l) {
+      const int nk = h->opts.smoother == DGMG_SMOOTHER_EA ? 1 : h->lv[l].dim;
+      for (int q = 0; q < nk; ++q) {
+        const int nd = h->opts.smoother == DGMG_SMOOTHER_EA ? -1 : q;
+        int np[3], NA, NL;
+        sweep_shape(h->lv[l], nd, np, NA, NL);
+        std::vector<int64_t> key{(int64_t)mg_size(h), h->lv[l].dim, NA, NL, np[0], np[1], np[2]};
+        int found = -1;
+        for (auto& s : seen)
+          if (s.first == key) found = s.second;
+        if (found >= 0) {
+          h->waves[l][nd < 0 ? 3 : nd] = found;
+          continue;
+        }
+        seen.emplace_back(key, -1);
+        // tune this handle's level fully, then record the choice of this sweep
+        int keep[NKIND];
+        for (int k = 0; k < NKIND; ++k) keep[k] = h->waves[l][k];
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        float best = 1e30f;
+        int bw = 0;
+        for (int w : {1, 2, 4}) {
+          const bool f32 = mixed(h);
+          auto launch = [&]() {
+            return f32 ? k_fdm<float>(h, l, nd, (const float*)h->buf[l].r, w)
+                       : k_fdm<double>(h, l, nd, (const double*)h->buf[l].r, w);
+          };
+          if (f32) k_fill_v<float>(h, (float*)h->buf[l].r, h->lv[l].n_dof);
+          else k_fill_v<double>(h, (double*)h->buf[l].r, h->lv[l].n_dof);
+          if ((rc = launch())) break;
+          (void)hipEventRecord(e0, h->stream);
+          for (int rep = 0; rep < 3 && !rc; ++rep) rc = launch();
+          (void)hipEventRecord(e1, h->stream);
+          if (rc || hipEventSynchronize(e1) != hipSuccess) {
+            rc = rc ? rc : DGMG_EHIP;
+            break;
+          }
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) {
+            best = ms;
+            bw = w;
+          }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return batch_fail(b, rc, "autotune: " + h->err);
+        for (int k = 0; k < NKIND; ++k) h->waves[l][k] = keep[k];
+        h->waves[l][nd < 0 ? 3 : nd] = bw;
+        h->tune_ms[l][nd < 0 ? 3 : nd] = best / 3.0f;
+        seen.back().second = bw;
+      }
+    }
+    drop_graphs(h);
+  }
+  for (auto& g : b->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  return DGMG_OK;
+}
+
+int dgmg_batch_use_graphs(dgmg_batch* b, int enable) {
+  if (!b) return DGMG_EINVAL;
+  for (auto& g : b->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  b->use_graphs = enable != 0;
+  return DGMG_OK;
+}
+
+// One MGCG phase for every grid: a graph whose per-grid chains are independent
+// child graphs (captured once, replayed each iteration; converged grids are
+// masked by their device flag), or eager launches.
+static int batch_phase(dgmg_batch* b, int which, double* x) {
+  const int n = (int)b->h.size();
+  if (!b->use_graphs) {
+    for (int i = 0; i < n; ++i) {
+      int rc = which == 0 ? pcg_phase_a(b->h[i], x + b->dof_off[i]) : pcg_phase_b(b->h[i]);
+      if (rc) return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);
+    }
+    return DGMG_OK;
+  }
+  if (which == 0 && b->gexec[0] && b->graph_x != x) {
+    (void)hipGraphExecDestroy(b->gexec[0]);
+    b->gexec[0] = nullptr;
+  }
+  if (!b->gexec[which]) {
+    hipGraph_t parent = nullptr;
+    if (hipGraphCreate(&parent, 0) != hipSuccess) return batch_fail(b, DGMG_EHIP, "graph create");
+    for (int i = 0; i < n; ++i) {
+      dgmg_handle* h = b->h[i];
+      hipGraph_t g = nullptr;
+      double* xi = x + b->dof_off[i];
+      int rc = capture(h, &g, [&]() { return which == 0 ? pcg_phase_a(h, xi) : pcg_phase_b(h); });
+      if (rc) {
+        (void)hipGraphDestroy(parent);
+        return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + h->err);
+      }
+      hipGraphNode_t node;
+      hipError_t e = hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(parent);
+        return batch_fail(b, DGMG_EHIP, std::string("child graph: ") + hipGetErrorString(e));
+      }
+    }
+    hipError_t e = hipGraphInstantiate(&b->gexec[which], parent, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(parent);
+    if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (which == 0) b->graph_x = x;
+  }
+  hipError_t e = hipGraphLaunch(b->gexec[which], b->stream);
+  return e == hipSuccess ? DGMG_OK : batch_fail(b, DGMG_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
+int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dgmg_stats* st) {
+  if (!b || !rhs || !x || !(tol >= 0)) return DGMG_EINVAL;
+  if (!b->bound) return batch_fail(b, DGMG_ENOMEM, "workspace not bound");
+  const int n = (int)b->h.size();
+  std::vector<double> r0(n), rmax(n), rn(n);
+  std::vector<int> its(n, 0), conv(n, 0);
+  if (st) std::memset(st, 0, sizeof(dgmg_stats) * n);
+  for (int i = 0; i < n; ++i) b->flags_host[i] = 1;
+  int rc = batch_flags_upload(b);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    if ((rc = pcg_init_a(b->h[i], rhs + b->dof_off[i], x + b->dof_off[i])))
+      return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);
+  if ((rc = batch_rr_download(b))) return rc;
+  int maxit = 0;
+  for (int i = 0; i < n; ++i) {
+    r0[i] = std::sqrt(b->rr_host[i]);
+    if (!std::isfinite(r0[i])) return batch_fail(b, DGMG_ENONFINITE, "grid " + std::to_string(i) + ": initial residual not finite");
+    rmax[i] = tol * r0[i];
+    rn[i] = r0[i];
+    conv[i] = r0[i] == 0.0;
+    b->flags_host[i] = conv[i] ? 0 : 1;
+    maxit = std::max(maxit, b->h[i]->opts.max_iter);
+    if (st) {
+      st[i].r0 = r0[i];
+      st[i].r_final = r0[i];
+      st[i].history[0] = r0[i];
+      st[i].converged = conv[i];
+    }
+  }
+  if ((rc = batch_flags_upload(b))) return rc;
+  for (int i = 0; i < n; ++i)
+    if ((rc = pcg_init_b(b->h[i]))) return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);
+  for (int it = 1; it <= maxit; ++it) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) any = any || b->flags_host[i];
+    if (!any) break;
+    if ((rc = batch_phase(b, 0, x))) return rc;
+    if ((rc = batch_rr_download(b))) return rc;
+    any = false;
+    for (int i = 0; i < n; ++i) {
+      if (!b->flags_host[i]) continue;
+      its[i] = it;
+      rn[i] = std::sqrt(b->rr_host[i]);
+      if (st) {
+        st[i].iterations = it;
+        st[i].r_final = rn[i];
+        if (it < 256) st[i].history[it] = rn[i];
+      }
+      if (!std::isfinite(rn[i])) return batch_fail(b, DGMG_ENONFINITE, "grid " + std::to_string(i) + ": residual not finite");
+      if (rn[i] <= rmax[i]) {
+        conv[i] = 1;
+        b->flags_host[i] = 0;
+      } else if (it >= b->h[i]->opts.max_iter) {
+        b->flags_host[i] = 0;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) break;
+    if ((rc = batch_flags_upload(b))) return rc;
+    if ((rc = batch_phase(b, 1, x))) return rc;
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, hipGetErrorString(e));
+  bool all = true;
+  for (int i = 0; i < n; ++i) {
+    all = all && conv[i];
+    if (st) {
+      st[i].converged = conv[i];
+      if (its[i] > 0) st[i].rho = std::pow(rn[i] / r0[i], 1.0 / its[i]);
+    }
+  }
+  return all ? DGMG_OK : DGMG_NOT_CONVERGED;
+}
+
+const char* dgmg_batch_last_error(const dgmg_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
+
+void dgmg_batch_destroy(dgmg_batch* b) {
+  if (!b) return;
+  for (auto& g : b->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto* h : b->h) dgmg_destroy(h);
+  if (b->flags_host) (void)hipHostFree(b->flags_host);
+  if (b->rr_host) (void)hipHostFree(b->rr_host);
+  delete b;
 }
 
 }  // extern "C"

@@ -42,9 +42,9 @@ bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
 
 template <class T, int DIM>
 int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx,
-                      int npy, int npz, hipStream_t s) {
+                      int npy, int npz, int waves, hipStream_t s) {
 #define DGMG_CASE(A, B) \
-  if (NA == A && NL == B) return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, s);
+  if (NA == A && NL == B) return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, s);
   DGMG_FDM_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;
@@ -67,8 +67,8 @@ int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T
                            hipStream_t s) {
 #define DGMG_CASE(F, C)                                                                          \
   if (Lf.NP == F && Lf.NPc == C)                                                                 \
-    return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, s)        \
-                     : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, s);
+    return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, Lf.active, s) \
+                     : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, Lf.active, s);
   DGMG_XFER_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;

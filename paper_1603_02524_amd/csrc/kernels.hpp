@@ -56,8 +56,11 @@ struct LevelDev {
   const T* D = nullptr;    // NP*NP, D[i*NP+k] = phi_k'(eta_i)
   const T* rho = nullptr;  // NP
   const T* J = nullptr;    // NP x NPc interpolation from the coarser level
+  const int* active = nullptr;  // batched solves: the kernels return at once when *active == 0
   DirDev<T> dir[3];
 };
+
+__device__ __forceinline__ bool inactive(const int* flag) { return flag != nullptr && *flag == 0; }
 
 // ---------------------------------------------------------------- block reduction
 __device__ __forceinline__ double wave_sum(double v) {
@@ -104,7 +107,7 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   T* sy = sx + EPB * NE;
   __shared__ double red[16];
   const int blk = xcd_block(nblk);
-  if (blk < 0) return;
+  if (blk < 0 || inactive(L.active)) return;
   const int e0 = blk * EPB;
   const int ne = imin(EPB, L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -360,7 +363,7 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   __shared__ T lv[3][NMAX];
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   const int pid = xcd_block(npatch);
-  if (pid < 0) return;
+  if (pid < 0 || inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NP = L.NP, NE = DIM == 3 ? NP * NP * NP : NP * NP;
   int p[3];
@@ -476,16 +479,18 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   }
 }
 
+// waves: wavefronts per block (1, 2 or 4; 0 = default), the shape the autotuner picks.
 template <class T, int DIM, int NA, int NL>
 int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
-                 hipStream_t s) {
+                 int waves, hipStream_t s) {
   constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL>), dim3(xcd_grid(npatch)),
-                     dim3(fdm_threads<NA, NL, DIM>()), shm, s, L, nd, r, out, npx, npy, npz);
+  const int th = (waves >= 1 && waves <= 4) ? 64 * waves : fdm_threads<NA, NL, DIM>();
+  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL>), dim3(xcd_grid(npatch)), dim3(th), shm, s, L, nd, r,
+                     out, npx, npy, npz);
   return 0;
 }
 
@@ -509,7 +514,7 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
   __shared__ int64_t cadr[EPB][3][NP][3];
   __shared__ int ccnt[EPB][3][NP];
   const int blk = xcd_block(nblk);
-  if (blk < 0) return;
+  if (blk < 0 || inactive(L.active)) return;
   const int e0 = blk * EPB;
   const int ne = imin(EPB, L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -582,7 +587,9 @@ constexpr int xfer_epb() {
 
 template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
 __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, int n_elem,
-                                                       const T* __restrict__ in, T* __restrict__ out) {
+                                                       const T* __restrict__ in, T* __restrict__ out,
+                                                       const int* __restrict__ active) {
+  if (inactive(active)) return;
   constexpr int NEF = ipow(NPF, DIM), NEC = ipow(NPC, DIM), EPB = xfer_epb<NPF, DIM>();
   constexpr int NIN = RESTRICT ? NPF : NPC, NOUT = RESTRICT ? NPC : NPF;
   constexpr int NEI = ipow(NIN, DIM), NEO = ipow(NOUT, DIM);
@@ -632,7 +639,7 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
 }
 
 template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
-int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, hipStream_t s) {
+int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* active, hipStream_t s) {
   constexpr int EPB = xfer_epb<NPF, DIM>();
   const int nb = (n_elem + EPB - 1) / EPB;
   const size_t shm = 2 * (size_t)EPB * ipow(NPF, DIM) * sizeof(T);
@@ -640,7 +647,7 @@ int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, hipStream_t s
     (void)hipFuncSetAttribute((const void*)transfer_kernel<T, DIM, NPF, NPC, RESTRICT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT>), dim3(nb), dim3(256), shm, s, J,
-                     n_elem, in, out);
+                     n_elem, in, out, active);
   return 0;
 }
 
@@ -650,7 +657,7 @@ struct Kern {
   static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
                    int* nblk, hipStream_t s);
   static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
-                 int npz, hipStream_t s);
+                 int npz, int waves, hipStream_t s);
   static bool fdm_supported(int NA, int NL);
   static int combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, hipStream_t s);

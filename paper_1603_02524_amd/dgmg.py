@@ -64,8 +64,22 @@ SIGNATURES = [
     ("dgmg_kernel_timing", c_int, [c_void_p, c_int]),
     ("dgmg_kernel_time", c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                  POINTER(c_double)]),
+    ("dgmg_use_graphs", c_int, [c_void_p, c_int]),
+    ("dgmg_autotune", c_int, [c_void_p]),
+    ("dgmg_tune_get", c_int, [c_void_p, c_int, c_int, POINTER(c_int), POINTER(c_double)]),
+    ("dgmg_tune_set", c_int, [c_void_p, c_int, c_int, c_int]),
     ("dgmg_destroy", None, [c_void_p]),
     ("dgmg_last_error", ctypes.c_char_p, [c_void_p]),
+    ("dgmg_batch_setup", c_int, [c_int, POINTER(DgmgGrid), POINTER(DgmgOpts), POINTER(c_void_p)]),
+    ("dgmg_batch_workspace_bytes", c_int, [c_void_p, POINTER(c_size_t)]),
+    ("dgmg_batch_bind_workspace", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("dgmg_batch_offsets", c_int, [c_void_p, POINTER(c_int64)]),
+    ("dgmg_batch_handle", c_int, [c_void_p, c_int, POINTER(c_void_p)]),
+    ("dgmg_batch_autotune", c_int, [c_void_p]),
+    ("dgmg_batch_use_graphs", c_int, [c_void_p, c_int]),
+    ("dgmg_batch_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, POINTER(DgmgStats)]),
+    ("dgmg_batch_last_error", ctypes.c_char_p, [c_void_p]),
+    ("dgmg_batch_destroy", None, [c_void_p]),
 ]
 
 _lib = None
@@ -260,10 +274,28 @@ class Solver:
         st = DgmgStats()
         rc = self._check(self.lib.dgmg_solve(self.h, self._ptr(rhs), self._ptr(x), float(tol),
                                              ctypes.byref(st)), allow=(0, 1))
-        n = st.iterations
-        return {"rc": rc, "iterations": n, "converged": bool(st.converged), "r0": st.r0,
-                "r_final": st.r_final, "rho": st.rho,
-                "history": [st.history[i] for i in range(min(n, 255) + 1)]}
+        return _stats_dict(st, rc)
+
+    def use_graphs(self, enable=True):
+        self._check(self.lib.dgmg_use_graphs(self.h, int(enable)))
+
+    def autotune(self):
+        """Time the patch-solve block shapes of every sweep and keep the fastest."""
+        self._check(self.lib.dgmg_autotune(self.h))
+        return self.tuning()
+
+    def tuning(self):
+        out = {}
+        for l in range(1, self.num_levels):
+            for kind in range(4):
+                w, ms = c_int(), c_double()
+                self._check(self.lib.dgmg_tune_get(self.h, l, kind, ctypes.byref(w), ctypes.byref(ms)))
+                if w.value:
+                    out[(l, kind)] = (w.value, ms.value)
+        return out
+
+    def set_tuning(self, level, kind, waves):
+        self._check(self.lib.dgmg_tune_set(self.h, level, kind, int(waves)))
 
     def kernel_timing(self, enable=True):
         self._check(self.lib.dgmg_kernel_timing(self.h, int(enable)))
@@ -273,3 +305,81 @@ class Solver:
         self._check(self.lib.dgmg_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
                                               ctypes.byref(by)))
         return {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}
+
+
+def _stats_dict(st, rc):
+    n = st.iterations
+    return {"rc": rc, "iterations": n, "converged": bool(st.converged), "r0": st.r0,
+            "r_final": st.r_final, "rho": st.rho,
+            "history": [st.history[i] for i in range(min(n, 255) + 1)]}
+
+
+class BatchSolver:
+    """Many independent grids solved in lock step (hipGraph replay per MGCG phase)."""
+
+    def __init__(self, problems, max_iter: int = 100, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        n = len(problems)
+        grids = (DgmgGrid * n)()
+        opts = (DgmgOpts * n)()
+        self._keep = []
+        for i, (g, m) in enumerate(problems):
+            gg, oo, keep = make_structs(g, m, max_iter)
+            grids[i] = gg
+            opts[i] = oo
+            self._keep.append(keep)
+        self._grids, self._opts = grids, opts
+        self.b = c_void_p()
+        rc = self.lib.dgmg_batch_setup(n, grids, opts, ctypes.byref(self.b))
+        if rc != 0:
+            raise DgmgError(rc, self.lib.dgmg_batch_last_error(None).decode())
+        self.count = n
+        nbytes = c_size_t()
+        self._check(self.lib.dgmg_batch_workspace_bytes(self.b, ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self._ws.device)
+        self._check(self.lib.dgmg_batch_bind_workspace(self.b, c_void_p(aligned), self.ws_bytes,
+                                                       c_void_p(self.stream.cuda_stream)))
+        off = (c_int64 * (n + 1))()
+        self._check(self.lib.dgmg_batch_offsets(self.b, off))
+        self.offsets = [int(off[i]) for i in range(n + 1)]
+        self.device = self._ws.device
+
+    def _check(self, rc, allow=(0,)):
+        if rc not in allow:
+            raise DgmgError(rc, self.lib.dgmg_batch_last_error(self.b).decode())
+        return rc
+
+    @property
+    def n_dof(self):
+        return self.offsets[-1]
+
+    def use_graphs(self, enable=True):
+        self._check(self.lib.dgmg_batch_use_graphs(self.b, int(enable)))
+
+    def autotune(self):
+        self._check(self.lib.dgmg_batch_autotune(self.b))
+
+    def solve(self, rhs, x, tol=1e-10):
+        for t in (rhs, x):
+            if t.dtype != self.torch.float64 or not t.is_contiguous() or t.numel() != self.n_dof:
+                raise ValueError("rhs and x must be contiguous float64 vectors of all grids")
+        st = (DgmgStats * self.count)()
+        rc = self._check(self.lib.dgmg_batch_solve(self.b, c_void_p(rhs.data_ptr()), c_void_p(x.data_ptr()),
+                                                   float(tol), st), allow=(0, 1))
+        return [_stats_dict(st[i], rc) for i in range(self.count)]
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.dgmg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,7 +23,7 @@ def _header_symbols():
 def test_library_exports_every_declared_symbol():
     lib = D.load_library()
     syms = _header_symbols()
-    assert len(syms) >= 20
+    assert len(syms) >= 34
     for s in syms:
         assert hasattr(lib, s), s
     assert sorted(n for n, _, _ in D.SIGNATURES) == syms
@@ -104,3 +104,42 @@ def test_level_series_and_geometry_match_oracle():
                 assert b"workspace" in lib.dgmg_last_error(h)
             finally:
                 lib.dgmg_destroy(h)
+
+
+def test_batch_layout_host_side():
+    """Batch setup (host only): member workspaces are disjoint, aligned and inside
+    the batch workspace; unknown offsets follow the member sizes."""
+    lib = D.load_library()
+    rng = np.random.default_rng(1)
+    probs = []
+    for P in (4, 6, 8, 2, 12, 3):
+        n = tuple(int(v) for v in rng.integers(1, 4, size=3))
+        probs.append((synth.Grid(3, tuple(rng.uniform(0.5, 1.5, n[d]) for d in range(3)), (False,) * 3),
+                      synth.Method(P=P, smoother="FA")))
+    k = len(probs)
+    grids = (D.DgmgGrid * k)()
+    opts = (D.DgmgOpts * k)()
+    keep = []
+    for i, (g, m) in enumerate(probs):
+        gg, oo, kk = D.make_structs(g, m)
+        grids[i], opts[i] = gg, oo
+        keep.append(kk)
+    b = ctypes.c_void_p()
+    assert lib.dgmg_batch_setup(k, grids, opts, ctypes.byref(b)) == 0
+    try:
+        total = ctypes.c_size_t()
+        assert lib.dgmg_batch_workspace_bytes(b, ctypes.byref(total)) == 0
+        sizes = []
+        for i in range(k):
+            h = ctypes.c_void_p()
+            assert lib.dgmg_batch_handle(b, i, ctypes.byref(h)) == 0
+            nb = ctypes.c_size_t()
+            assert lib.dgmg_workspace_bytes(h, ctypes.byref(nb)) == 0
+            sizes.append(nb.value)
+        assert total.value >= sum(sizes)
+        off = (ctypes.c_int64 * (k + 1))()
+        assert lib.dgmg_batch_offsets(b, off) == 0
+        for i, (g, m) in enumerate(probs):
+            assert off[i + 1] - off[i] == g.n_dof(m.P)
+    finally:
+        lib.dgmg_batch_destroy(b)

