@@ -40,6 +40,10 @@ def _workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _time_solves(S, rhs, x, tol, warmup, steps, timing):
     import torch
     st = None
@@ -109,12 +113,15 @@ def main():
 
     w = _workload(args.workload)
     g, m = w.grid, w.method
+    _log(f"setup {w.name}")
     S = dgmg.Solver(g, m, max_iter=200)
     n = S.n_dof()
     rhs_np = synth.rhs_uniform(w.seed, n)
     rhs = torch.tensor(rhs_np, dtype=torch.float64, device="cuda")
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    _log("timing FP64 solves")
     sec, st, kt = _time_solves(S, rhs, x, w.tol, args.warmup, args.steps, timing=True)
+    _log(f"FP64: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
     # true residual of the final iterate (outside the timed region)
     r = S.residual(S.num_levels - 1, rhs, x)
     true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(rhs))
@@ -144,6 +151,7 @@ def main():
            "roofline": roof}
 
     if not args.no_mixed:
+        _log("timing mixed-precision solves")
         wm = synth.with_method(w, precision="mixed")
         Sm = dgmg.Solver(wm.grid, wm.method, max_iter=200)
         xm = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -156,6 +164,7 @@ def main():
         Sm.close()
 
     if not args.no_cpu_baseline:
+        _log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = _cpu_baseline(w, rhs_np, st["iterations"], args.cpu_sample_iters)
     S.close()
     print(json.dumps(out), flush=True)
