@@ -29,7 +29,8 @@
  *   otherwise.  A handle must not be used from two host threads at once.
  * dtype: DGMG_F64 (double) or DGMG_F32 (float) selects the element type of
  *   the vector arguments of level operations; tables exist in both precisions.
- * Errors: 0 on success; > 0 non-fatal status (DGMG_NOT_CONVERGED); < 0 error
+ * Errors: 0 on success; > 0 non-fatal status (DGMG_NOT_CONVERGED,
+ *   DGMG_FELLBACK); < 0 error
  *   (DGMG_EINVAL bad argument, DGMG_EHIP runtime failure, DGMG_ENOMEM
  *   workspace missing or too small, DGMG_EUNSUPPORTED configuration not
  *   built, DGMG_ENONFINITE NaN/Inf met).  dgmg_last_error() returns the
@@ -48,6 +49,7 @@ extern "C" {
 
 #define DGMG_OK 0
 #define DGMG_NOT_CONVERGED 1
+#define DGMG_FELLBACK 2 /* learned weights rejected by the probe; fixed weights kept */
 #define DGMG_EINVAL (-1)
 #define DGMG_EHIP (-2)
 #define DGMG_ENOMEM (-3)
@@ -90,7 +92,7 @@ typedef struct {
 } dgmg_grid;
 
 typedef struct {
-  int P;             /* top-level order, 1 <= P <= 16 */
+  int P;             /* top-level order, 1 <= P <= 32 (kernels for P_l in 1,2,3,4,6,8,12,16,32) */
   int flux;          /* DGMG_FLUX_IP or DGMG_FLUX_LDG */
   double beta[3];    /* LDG parameter per direction (Sec. 2.3); ignored for IP */
   double mu_star;    /* penalty factor mu_star > 0 of mu = mu_0 (1 + mu_star) */
@@ -165,6 +167,14 @@ int dgmg_residual(dgmg_handle* h, int level, const void* f, const void* x, void*
  * (eq. (correction:global), eq. (weight function:ec), eq. (weight
  * function:fc)).  u is updated in place; f unchanged. */
 int dgmg_smooth(dgmg_handle* h, int level, void* u, const void* f, int nsteps, int dtype);
+
+/* One additive Schwarz sweep over one partition of level l >= 1 (Sec. 3.1):
+ * u += sum_s R_s^T (w_s (.) A_ss^{-1} R_s (f - A_l u)).  normal = -1: the
+ * element-centred partition; normal = d: the face-centred partition with
+ * faces normal to direction d.  Either kind may be used whatever the
+ * handle's smoother (DGMG_EUNSUPPORTED if no patch kernel exists for the
+ * tile).  Uses the level's internal residual scratch. */
+int dgmg_sweep(dgmg_handle* h, int level, void* u, const void* f, int normal, int dtype);
 
 /* f_{l-1} = I_l^T r_l: restriction by the transpose of the embedded
  * interpolation (Sec. 3.2).  level >= 1. */
@@ -258,6 +268,88 @@ int dgmg_batch_use_graphs(dgmg_batch* b, int enable);
 int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dgmg_stats* st);
 const char* dgmg_batch_last_error(const dgmg_batch* b);
 void dgmg_batch_destroy(dgmg_batch* b);
+
+/* ---------------------------------------------------------- learned weights
+ * Extension beyond the paper.  The face-centred smoother (FA) may replace the
+ * fixed normal weights of its patches (eq. (weight function:fc) of Sec. 3.1,
+ * read as w_F = 1/2 [1 + phi(1 - |xi_F|)]) by weights with a transition width
+ * theta_f and a damping factor omega_f per face f:
+ *   w_f = omega_f wt_f / (sum of wt_f' over the patches of the same
+ *         orientation that cover the node),  wt_f = 1/2 [1 + phi((1 - |xi_F|) / theta_f)].
+ * The normalisation keeps a partition of unity for omega = 1 whatever the
+ * widths; theta = omega = 1 gives the fixed weights.  Lateral (element-centred)
+ * weights are unchanged.
+ *
+ * Faces are enumerated level by level (l = 1 .. L, the smoothing levels),
+ * then by normal direction d = 0 .. D-1, then face f = 0 .. nf_d - 1
+ * (nf_d = N_d periodic, N_d + 1 Dirichlet; face f lies between elements f-1
+ * and f).  A small MLP maps per-face features to (theta, omega):
+ *   x (DGMG_MLP_IN) -> tanh(W1 x + b1) -> tanh(W2 h1 + b2) (DGMG_MLP_HIDDEN each)
+ *   -> y = W3 h2 + b3 (DGMG_MLP_OUT),
+ *   theta = THETA_MIN + (THETA_MAX - THETA_MIN) sigmoid(y0),
+ *   omega = OMEGA_MIN + (OMEGA_MAX - OMEGA_MIN) sigmoid(y1).
+ * Parameter vector (FP32, DGMG_MLP_PARAMS values): W1 (HIDDEN x IN, row-major),
+ * b1, W2 (HIDDEN x HIDDEN), b2, W3 (OUT x HIDDEN), b3.  Features per face:
+ *   P_l / 32, log2(dx_left / h_lat) / 5, log2(dx_right / h_lat) / 5,
+ *   1 on a Dirichlet boundary face else 0, D - 2, N_O,l / (P_l + 1),
+ * with dx_left / dx_right the normal sizes of the adjoining elements (the
+ * existing one at a boundary face) and h_lat the geometric mean of all element
+ * sizes of the other directions. */
+#define DGMG_MLP_IN 6
+#define DGMG_MLP_HIDDEN 64
+#define DGMG_MLP_OUT 2
+#define DGMG_MLP_PARAMS 4738
+#define DGMG_THETA_MIN 0.25
+#define DGMG_THETA_MAX 2.0
+#define DGMG_OMEGA_MIN 0.5
+#define DGMG_OMEGA_MAX 1.5
+
+/* Number of faces of all smoothing levels (the length of the per-face arrays
+ * below), or DGMG_EINVAL.  Host only; needs no workspace. */
+int dgmg_face_count(const dgmg_handle* h);
+/* Features of every face, host float array [count][DGMG_MLP_IN]. */
+int dgmg_face_features(const dgmg_handle* h, float* X);
+/* Impose (theta, omega) per face (host arrays of dgmg_face_count doubles,
+ * finite and > 0), or restore the fixed weights with theta = omega = NULL.
+ * FA smoother only (else DGMG_EUNSUPPORTED); needs a bound workspace;
+ * synchronises the stream.  Captured graphs stay valid (tables are
+ * overwritten in place). */
+int dgmg_set_face_params(dgmg_handle* h, const double* theta, const double* omega);
+/* Current (theta, omega) per face into host arrays; returns 1 when learned
+ * parameters are in use, 0 for the fixed weights (all ones reported). */
+int dgmg_get_face_params(const dgmg_handle* h, double* theta, double* omega);
+
+/* MLP kernels (FP32, on `stream`; all arrays device, row-major, caller-owned).
+ * forward: X [B][IN] -> Y [B][OUT]; work [B][2 HIDDEN] receives h1, h2.
+ * backward: gradient of L = (1/B) sum_b sum_o (Y_bo - T_bo)^2 with respect to
+ *   the parameters into grad [PARAMS] (overwritten), from the X, Y, work of the
+ *   matching forward call; scratch holds B (2 HIDDEN + OUT) floats.  Sums over
+ *   the batch run in sample order (reproducible).
+ * adam: one Adam step (Kingma and Ba) on n parameters at step t >= 1:
+ *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * dgmg_mlp_param_count returns DGMG_MLP_PARAMS. */
+int dgmg_mlp_param_count(void);
+int dgmg_mlp_forward(const float* params, const float* X, int B, float* Y, float* work, void* stream);
+int dgmg_mlp_backward(const float* params, const float* X, const float* T, int B, const float* Y,
+                      const float* work, float* grad, float* scratch, void* stream);
+int dgmg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, int t, float lr, float b1,
+                  float b2, float eps, void* stream);
+
+/* Device work bytes needed by dgmg_apply_mlp on this handle. */
+int dgmg_mlp_work_bytes(const dgmg_handle* h, size_t* bytes);
+/* Learned weights with fallback: evaluate the MLP (device params) on the
+ * handle's face features, then probe both weight sets with probe_iters MGCG
+ * iterations from x = 0 on a fixed pseudo-random right-hand side (the same for
+ * both).  Keeps the learned weights when their residual reduction
+ * ||r_k|| / ||r_0|| is no worse than that of the fixed weights (DGMG_OK), else
+ * restores the fixed weights and returns DGMG_FELLBACK (also when the MLP
+ * output is not finite or the probe breaks down).  work: device buffer of
+ * dgmg_mlp_work_bytes bytes, 256-byte aligned.  ratios (host, may be NULL)
+ * receives {learned, fixed} reductions.  Single (non-batch) handles; FA only;
+ * synchronises. */
+int dgmg_apply_mlp(dgmg_handle* h, const float* params, void* work, size_t bytes, int probe_iters,
+                   double* ratios);
 
 #ifdef __cplusplus
 }

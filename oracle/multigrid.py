@@ -74,7 +74,12 @@ class Level:
 class Hierarchy:
     """All levels of one problem; vectors are lexicographic flat FP64 arrays."""
 
-    def __init__(self, grid, method, patch_mode: str = "fdm", assemble: bool = True):
+    def __init__(self, grid, method, patch_mode: str = "fdm", assemble: bool = True, face_params=None,
+                 coarse: bool = True):
+        """face_params: optional {level: [(theta[nf], omega[nf]) per direction]} for the
+        face-centred normal weights (learned-weight variant; see fc_patches_1d).
+        coarse=False skips the coarse LU and assembly (level operations only, for
+        grids too large for a sparse direct solve)."""
         self.grid = grid
         self.method = method
         self.orders = level_orders(method.P)
@@ -83,7 +88,7 @@ class Hierarchy:
         for l, Pl in enumerate(self.orders):
             ops = [operators_1d(Pl, np.asarray(grid.dx[d]), grid.periodic[d], betas[d], method.mu_star)
                    for d in range(grid.dim)]
-            A = assemble_kron(grid, Pl, betas, method.mu_star) if (assemble or l == 0) else None
+            A = assemble_kron(grid, Pl, betas, method.mu_star) if (assemble or (l == 0 and coarse)) else None
             sm = None
             if l > 0:
                 if A is not None:
@@ -91,11 +96,14 @@ class Hierarchy:
                 else:
                     applyA = (lambda P_, ops_: (lambda u: apply_kron(grid, P_, u, ops=ops_)))(Pl, ops)
                 sm = SmootherLevel(grid, Pl, overlap_for(Pl, method.overlap), method.weighting,
-                                   method.smoother, applyA, A, ops, mode=patch_mode)
+                                   method.smoother, applyA, A, ops, mode=patch_mode,
+                                   face_params=None if face_params is None else face_params.get(l))
             self.levels.append(Level(Pl, A, sm, ops))
         A0 = self.levels[0].A
         self.periodic_any = all(grid.periodic)
-        if self.periodic_any:
+        if not coarse:
+            self._lu0 = None
+        elif self.periodic_any:
             # pin the first unknown, solve, then remove the mean (min-norm solution)
             self._lu0 = spla.splu(sp.csc_matrix(A0[1:, 1:]))
         else:

@@ -29,8 +29,9 @@ per orientation d = 1..D in sequence, the residual recomputed before each.
 """
 from __future__ import annotations
 
+import itertools
 from dataclasses import dataclass, field
-from typing import Dict, List, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 import scipy.linalg as sla
@@ -73,6 +74,15 @@ def w_face(xi_f, kind):
     return 0.5 * (1.0 + phi(1.0 - np.abs(xi_f), kind))
 
 
+def w_face_theta(xi_f, theta, kind):
+    """w_F with transition width theta: 1/2 [1 + phi((1 - |xi_F|) / theta)] (theta = 1: w_F).
+
+    Not in the paper: the learned-weight variant scales the transition of the
+    face weight; the resulting weights are renormalised per node (fc_patches_1d).
+    """
+    return 0.5 * (1.0 + phi((1.0 - np.abs(xi_f)) / theta, kind))
+
+
 # --------------------------------------------------------------------------- 1D patch sets
 
 @dataclass
@@ -109,7 +119,14 @@ def ec_patches_1d(P: int, N: int, periodic: bool, n_o: int, kind: str) -> List[P
     return out
 
 
-def fc_patches_1d(P: int, N: int, periodic: bool, kind: str) -> List[Patch1D]:
+def fc_patches_1d(P: int, N: int, periodic: bool, kind: str, theta=None, omega=None) -> List[Patch1D]:
+    """Face-centred patches normal to one direction, one per face.
+
+    With theta / omega (one value per face) the normal weights are
+    w_f = omega_f * w_F(xi; theta_f) / sum_{f' covering the node} w_F(xi'; theta_f'),
+    so that for omega = 1 the patches of one orientation still sum to one at
+    every node (a partition of unity) whatever the per-face widths are.
+    """
     eta, _ = gll(P)
     NP = P + 1
     out = []
@@ -128,8 +145,16 @@ def fc_patches_1d(P: int, N: int, periodic: bool, kind: str) -> List[Patch1D]:
         i = g_raw - mm * NP
         xi = eta[i]
         xi_f = np.where(mm == f - 1, xi - 1.0, xi + 1.0)
-        w = w_face(xi_f, kind)
+        w = w_face(xi_f, kind) if theta is None else w_face_theta(xi_f, float(theta[f]), kind)
         out.append(Patch1D(idx.astype(np.int64), w))
+    if theta is not None:
+        total = np.zeros(N * NP)
+        for p in out:
+            np.add.at(total, p.idx, p.w)
+        om = np.ones(nf) if omega is None else np.asarray(omega, dtype=np.float64)
+        out = [Patch1D(p.idx, om[f] * p.w / total[p.idx]) for f, p in enumerate(out)]
+    elif omega is not None:
+        out = [Patch1D(p.idx, float(omega[f]) * p.w) for f, p in enumerate(out)]
     return out
 
 
@@ -167,6 +192,7 @@ class SmootherLevel:
     mode: str = "fdm"        # "fdm" or "dense"
     ec: list = field(default_factory=list)     # per direction list[Patch1D]
     fc: list = field(default_factory=list)
+    face_params: Optional[list] = None        # per direction (theta[nf], omega[nf]) or None
     _eig: Dict = field(default_factory=dict)
     _chol: Dict = field(default_factory=dict)
 
@@ -174,7 +200,8 @@ class SmootherLevel:
         g = self.grid
         for d in range(g.dim):
             self.ec.append(ec_patches_1d(self.P, g.n[d], g.periodic[d], self.n_o, self.kind))
-            self.fc.append(fc_patches_1d(self.P, g.n[d], g.periodic[d], self.kind))
+            th, om = (None, None) if self.face_params is None else self.face_params[d]
+            self.fc.append(fc_patches_1d(self.P, g.n[d], g.periodic[d], self.kind, th, om))
 
     @property
     def shape(self):
@@ -272,6 +299,39 @@ class SmootherLevel:
                 w = w * p1[d].w.reshape(sh)
             corr[ix] += w * du          # indices are distinct within one patch
         return u + corr.reshape(-1)
+
+    def sweep_at(self, u: np.ndarray, f: np.ndarray, normal: int, nodes, r: np.ndarray = None) -> np.ndarray:
+        """Values at the lexicographic indices `nodes` after one sweep (as `sweep`),
+        computed from the patches that cover each node only: for grids too large
+        for a full sweep in numpy.  r: the residual f - A u if already known."""
+        dim = self.grid.dim
+        shape = self.shape
+        if r is None:
+            r = f - self.apply_A(u)
+        r = np.asarray(r).reshape(shape)
+        out = []
+        for node in nodes:
+            coords = np.unravel_index(int(node), shape)          # slowest direction first
+            g = [int(coords[dim - 1 - d]) for d in range(dim)]
+            cover = []
+            for d in range(dim):
+                kind = "fc" if d == normal else "ec"
+                pts = self.fc[d] if kind == "fc" else self.ec[d]
+                cover.append([(kind, k, int(np.nonzero(p.idx == g[d])[0][0]))
+                              for k, p in enumerate(pts) if np.any(p.idx == g[d])])
+            val = float(np.asarray(u).reshape(-1)[int(node)])
+            for combo in itertools.product(*cover):
+                sig = tuple((c[0], c[1]) for c in combo)
+                p1 = [self.patch_1d(d, sig[d]) for d in range(dim)]
+                ix = np.ix_(*[p1[d].idx for d in reversed(range(dim))])
+                du = self.solve_patch(sig, r[ix], None)
+                pos = tuple(combo[d][2] for d in reversed(range(dim)))
+                w = 1.0
+                for d in range(dim):
+                    w *= p1[d].w[combo[d][2]]
+                val += w * du[pos]
+            out.append(val)
+        return np.asarray(out)
 
     def smooth(self, u: np.ndarray, f: np.ndarray, steps: int) -> np.ndarray:
         """`steps` Schwarz iterations (EA: one sweep each; FA: one sweep per direction)."""

@@ -23,7 +23,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-HIP_UNITS = ["dgmg.hip", "inst_f64_3d.hip", "inst_f32_3d.hip", "inst_f64_2d.hip", "inst_f32_2d.hip"]
+HIP_UNITS = ["dgmg.hip", "mlp.hip", "inst_f64_3d.hip", "inst_f32_3d.hip", "inst_f64_2d.hip", "inst_f32_2d.hip"]
 CXX_UNITS = ["setup.cpp"]
 
 

@@ -11,6 +11,7 @@
 
 #include "../../include/dgmg.h"
 #include "kernels.hpp"
+#include "kernels_big.hpp"
 #include "setup.hpp"
 
 using namespace dgmg;
@@ -126,6 +127,20 @@ __global__ void __launch_bounds__(VEC_THREADS) k_fill(T* __restrict__ a, T v, in
     a[i] = v;
 }
 
+// Deterministic pseudo-random values in [-1, 1) from the index (integer hash
+// with the lowbias32 constants of C. Wellons), used as the probe right-hand side.
+__global__ void __launch_bounds__(VEC_THREADS) k_fill_hash(double* __restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i ^ (uint32_t)(i >> 32) ^ 0x9e3779b9u;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    a[i] = (double)(x >> 8) * (1.0 / 8388608.0) - 1.0;
+  }
+}
+
 __global__ void __launch_bounds__(VEC_THREADS) k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n, const int* act) {
   if (inactive(act)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -206,7 +221,7 @@ inline unsigned vec_blocks(int64_t n) {
 }  // namespace
 
 // =================================================================== handle
-constexpr int MAXL = 8;      // levels: P <= 16 gives at most 6
+constexpr int MAXL = 8;      // levels: P <= 32 gives at most 6
 constexpr int NKIND = 4;     // sweep kinds: 0..2 face-centred normal d, 3 element-centred
 
 struct dgmg_handle {
@@ -244,6 +259,8 @@ struct dgmg_handle {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   const double* graph_x = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only while capturing
+  // per-face (theta, omega) of the face-centred normal weights; empty = the fixed weights
+  std::vector<double> face_theta, face_omega;
   // autotuned patch-solve block shapes (waves per block), 0 = default
   int waves[MAXL][NKIND] = {};
   float tune_ms[MAXL][NKIND] = {};
@@ -422,6 +439,9 @@ void layout(dgmg_handle* h, char* base, Upload* up) {
     }
   }
   pmax = std::max(pmax, (size_t)l0.n_dof);
+  for (int l = 1; l < nl; ++l)  // scratch of the two-kernel transfers of large 3D elements
+    if (h->lv[l].dim == 3 && h->lv[l].NP == BIG_NP)
+      pmax = std::max(pmax, (size_t)transfer_big_scratch((int)h->lv[l].n_elem, h->lv[l].NP, h->lv[l].NPc));
   h->patch_elems = pmax;
   h->patch = cv.take(pmax * sizeof(double));
   const size_t n0 = l0.n_dof;
@@ -540,8 +560,9 @@ int k_smooth(dgmg_handle* h, int l, T* u, const T* f, int steps, T* r) {
 template <class T>
 int k_transfer(dgmg_handle* h, int l, bool restr, const T* in, T* out) {
   const LevelDev<T>& L = LD<T>(h, l);
-  int rc = L.dim == 3 ? Kern<T, 3>::transfer(L, restr, in, out, h->stream)
-                      : Kern<T, 2>::transfer(L, restr, in, out, h->stream);
+  T* tmp = (T*)h->patch;
+  int rc = L.dim == 3 ? Kern<T, 3>::transfer(L, restr, in, out, tmp, h->stream)
+                      : Kern<T, 2>::transfer(L, restr, in, out, tmp, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no transfer kernel for this order pair");
   return check_hip(h, "transfer");
 }
@@ -813,9 +834,9 @@ int check_level(dgmg_handle* h, int level, int minl = 0) {
 int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   if (!g || !o) return fail(nullptr, DGMG_EINVAL, "null argument");
   if (g->dim != 2 && g->dim != 3) return fail(nullptr, DGMG_EINVAL, "dim must be 2 or 3");
-  const int okP[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  const int okP[] = {1, 2, 3, 4, 6, 8, 12, 16, 32};
   if (std::find(std::begin(okP), std::end(okP), o->P) == std::end(okP))
-    return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16");
+    return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16, 32");
   if (!(o->mu_star > 0) || !std::isfinite(o->mu_star)) return fail(nullptr, DGMG_EINVAL, "mu_star must be > 0");
   if (o->flux != DGMG_FLUX_IP && o->flux != DGMG_FLUX_LDG) return fail(nullptr, DGMG_EINVAL, "bad flux");
   if (o->smoother != DGMG_SMOOTHER_EA && o->smoother != DGMG_SMOOTHER_FA) return fail(nullptr, DGMG_EINVAL, "bad smoother");
@@ -1052,6 +1073,20 @@ int dgmg_smooth(dgmg_handle* h, int level, void* u, const void* f, int nsteps, i
   return k_smooth<float>(h, level, (float*)u, (const float*)f, nsteps, (float*)h->buf[level].r);
 }
 
+int dgmg_sweep(dgmg_handle* h, int level, void* u, const void* f, int normal, int dtype) {
+  int rc = need_bound(h);
+  if (rc || (rc = check_level(h, level, 1))) return rc;
+  const LevelHost& lv = h->lv[level];
+  if (!u || !f || normal < -1 || normal >= lv.dim) return fail(h, DGMG_EINVAL, "bad arguments");
+  int np[3], NA, NL;
+  sweep_shape(lv, normal, np, NA, NL);
+  const bool ok = lv.dim == 3 ? Kern<double, 3>::fdm_supported(NA, NL) : Kern<double, 2>::fdm_supported(NA, NL);
+  if (!ok) return fail(h, DGMG_EUNSUPPORTED, "no patch kernel for this sweep");
+  if (dtype == DGMG_F64)
+    return k_sweep<double>(h, level, normal, (double*)u, (const double*)f, (double*)h->buf[level].r);
+  return k_sweep<float>(h, level, normal, (float*)u, (const float*)f, (float*)h->buf[level].r);
+}
+
 int dgmg_restrict(dgmg_handle* h, int level, const void* rf, void* fc, int dtype) {
   int rc = need_bound(h);
   if (rc || (rc = check_level(h, level, 1))) return rc;
@@ -1202,6 +1237,190 @@ void dgmg_destroy(dgmg_handle* h) {
 }
 
 const char* dgmg_last_error(const dgmg_handle* h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
+
+// ------------------------------------------------------------ learned face weights
+}  // extern "C"
+
+namespace {
+
+// Upload the face-centred normal weights of every smoothing level (FP64 and
+// FP32 tables): the fixed weights when theta is null, else the parametrised ones.
+int upload_face_weights(dgmg_handle* h, const double* theta, const double* omega) {
+  std::vector<std::vector<char>> keep;
+  size_t off = 0;
+  for (size_t l = 1; l < h->lv.size(); ++l) {
+    const LevelHost& lv = h->lv[l];
+    for (int d = 0; d < lv.dim; ++d) {
+      const Dir1D& dd = lv.dir[d];
+      std::vector<double> w;
+      if (theta) fc_weights_param(lv, d, h->sp.weighting, theta + off, omega + off, w);
+      else w = dd.w_fc;
+      off += dd.nf;
+      std::vector<char> b64(w.size() * sizeof(double)), b32(w.size() * sizeof(float));
+      std::memcpy(b64.data(), w.data(), b64.size());
+      float* f = reinterpret_cast<float*>(b32.data());
+      for (size_t i = 0; i < w.size(); ++i) f[i] = (float)w[i];
+      hipError_t e = hipMemcpyAsync((void*)h->Ld[l].dir[d].w_fc, b64.data(), b64.size(), hipMemcpyHostToDevice,
+                                    h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((void*)h->Lf[l].dir[d].w_fc, b32.data(), b32.size(), hipMemcpyHostToDevice, h->stream);
+      if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("weight upload: ") + hipGetErrorString(e));
+      keep.push_back(std::move(b64));
+      keep.push_back(std::move(b32));
+    }
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("weight upload sync: ") + hipGetErrorString(e));
+  if (theta) {
+    h->face_theta.assign(theta, theta + off);
+    h->face_omega.assign(omega, omega + off);
+  } else {
+    h->face_theta.clear();
+    h->face_omega.clear();
+  }
+  return DGMG_OK;
+}
+
+struct MlpWork {
+  float *X, *Y, *hid;
+  double *rhs, *x;
+  size_t bytes;
+};
+
+MlpWork mlp_layout(const dgmg_handle* h, char* base) {
+  const size_t nf = (size_t)face_count(h->lv), n = (size_t)h->lv.back().n_dof;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  MlpWork w{};
+  size_t o = 0;
+  w.X = (float*)(base + o);
+  o += al(nf * DGMG_MLP_IN * sizeof(float));
+  w.Y = (float*)(base + o);
+  o += al(nf * DGMG_MLP_OUT * sizeof(float));
+  w.hid = (float*)(base + o);
+  o += al(nf * 2 * DGMG_MLP_HIDDEN * sizeof(float));
+  w.rhs = (double*)(base + o);
+  o += al(n * sizeof(double));
+  w.x = (double*)(base + o);
+  o += al(n * sizeof(double));
+  w.bytes = o;
+  return w;
+}
+
+// ||r_k|| / ||r_0|| after k PCG iterations from x = 0 on the probe right-hand side;
+// +inf when the iteration breaks down (non-finite norms).
+int probe_ratio(dgmg_handle* h, const MlpWork& w, int iters, double* ratio) {
+  const int64_t n = h->lv.back().n_dof;
+  hipLaunchKernelGGL(k_fill_hash, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, w.rhs, n);
+  k_fill_v<double>(h, w.x, n);
+  const int save = h->opts.max_iter;
+  h->opts.max_iter = iters;
+  dgmg_stats st;
+  int rc = dgmg_solve(h, w.rhs, w.x, 0.0, &st);
+  h->opts.max_iter = save;
+  if (rc == DGMG_ENONFINITE) {
+    *ratio = INFINITY;
+    return DGMG_OK;
+  }
+  if (rc < 0) return rc;
+  *ratio = st.r0 > 0 ? st.r_final / st.r0 : 0.0;
+  if (!std::isfinite(*ratio)) *ratio = INFINITY;
+  return DGMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgmg_face_count(const dgmg_handle* h) {
+  if (!h) return DGMG_EINVAL;
+  return face_count(h->lv);
+}
+
+int dgmg_face_features(const dgmg_handle* h, float* X) {
+  if (!h || !X) return DGMG_EINVAL;
+  std::vector<double> f;
+  face_features(h->lv, f);
+  for (size_t i = 0; i < f.size(); ++i) X[i] = (float)f[i];
+  return DGMG_OK;
+}
+
+int dgmg_set_face_params(dgmg_handle* h, const double* theta, const double* omega) {
+  int rc = need_bound(h);
+  if (rc) return rc;
+  if (h->opts.smoother != DGMG_SMOOTHER_FA)
+    return fail(h, DGMG_EUNSUPPORTED, "face parameters need the face-centred smoother");
+  if ((theta == nullptr) != (omega == nullptr)) return fail(h, DGMG_EINVAL, "theta and omega go together");
+  if (theta) {
+    const int n = face_count(h->lv);
+    for (int i = 0; i < n; ++i)
+      if (!(theta[i] > 0.0) || !(omega[i] > 0.0) || !std::isfinite(theta[i]) || !std::isfinite(omega[i]))
+        return fail(h, DGMG_EINVAL, "theta and omega must be finite and > 0");
+  }
+  return upload_face_weights(h, theta, omega);
+}
+
+int dgmg_get_face_params(const dgmg_handle* h, double* theta, double* omega) {
+  if (!h || !theta || !omega) return DGMG_EINVAL;
+  const int n = face_count(h->lv);
+  for (int i = 0; i < n; ++i) {
+    theta[i] = h->face_theta.empty() ? 1.0 : h->face_theta[i];
+    omega[i] = h->face_omega.empty() ? 1.0 : h->face_omega[i];
+  }
+  return h->face_theta.empty() ? 0 : 1;
+}
+
+int dgmg_mlp_work_bytes(const dgmg_handle* h, size_t* bytes) {
+  if (!h || !bytes) return DGMG_EINVAL;
+  *bytes = mlp_layout(h, nullptr).bytes;
+  return DGMG_OK;
+}
+
+int dgmg_apply_mlp(dgmg_handle* h, const float* params, void* work, size_t bytes, int probe_iters,
+                   double* ratios) {
+  int rc = need_bound(h);
+  if (rc) return rc;
+  if (!params || !work || probe_iters < 1) return fail(h, DGMG_EINVAL, "bad arguments");
+  if (h->active) return fail(h, DGMG_EINVAL, "handle belongs to a batch");
+  if (h->opts.smoother != DGMG_SMOOTHER_FA)
+    return fail(h, DGMG_EUNSUPPORTED, "learned weights need the face-centred smoother");
+  if (((uintptr_t)work) & 255) return fail(h, DGMG_EINVAL, "work must be 256-byte aligned");
+  const MlpWork w = mlp_layout(h, (char*)work);
+  if (bytes < w.bytes) return fail(h, DGMG_ENOMEM, "MLP work buffer too small");
+  const int nf = face_count(h->lv);
+  // network outputs per face
+  std::vector<double> feat;
+  face_features(h->lv, feat);
+  std::vector<float> X(feat.begin(), feat.end()), Y((size_t)nf * DGMG_MLP_OUT);
+  hipError_t e = hipMemcpyAsync(w.X, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("feature upload: ") + hipGetErrorString(e));
+  if ((rc = dgmg_mlp_forward(params, w.X, nf, w.Y, w.hid, h->stream))) return fail(h, rc, "MLP forward");
+  e = hipMemcpyAsync(Y.data(), w.Y, Y.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("MLP readback: ") + hipGetErrorString(e));
+  std::vector<double> theta(nf), omega(nf);
+  bool finite = true;
+  for (int i = 0; i < nf; ++i) {
+    const double y0 = Y[2 * i], y1 = Y[2 * i + 1];
+    finite = finite && std::isfinite(y0) && std::isfinite(y1);
+    theta[i] = DGMG_THETA_MIN + (DGMG_THETA_MAX - DGMG_THETA_MIN) / (1.0 + std::exp(-y0));
+    omega[i] = DGMG_OMEGA_MIN + (DGMG_OMEGA_MAX - DGMG_OMEGA_MIN) / (1.0 + std::exp(-y1));
+  }
+  // probe: fixed weights first, then the learned ones
+  double rf = 0, rl = INFINITY;
+  if ((rc = upload_face_weights(h, nullptr, nullptr))) return rc;
+  if ((rc = probe_ratio(h, w, probe_iters, &rf))) return rc;
+  if (finite) {
+    if ((rc = upload_face_weights(h, theta.data(), omega.data()))) return rc;
+    if ((rc = probe_ratio(h, w, probe_iters, &rl))) return rc;
+  }
+  if (ratios) {
+    ratios[0] = rl;
+    ratios[1] = rf;
+  }
+  if (finite && rl <= rf) return DGMG_OK;
+  if ((rc = upload_face_weights(h, nullptr, nullptr))) return rc;
+  return DGMG_FELLBACK;
+}
 
 // ------------------------------------------------------------------- batches
 int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, dgmg_batch** out) {

@@ -3,13 +3,16 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "kernels_big.hpp"
 
 namespace dgmg {
 
-// Orders with kernels: P in {1, 2, 3, 4, 6, 8, 12, 16}  (NP = P + 1).
-#define DGMG_NP_LIST(X) X(2) X(3) X(4) X(5) X(7) X(9) X(13) X(17)
+// Orders with kernels: P in {1, 2, 3, 4, 6, 8, 12, 16, 32}  (NP = P + 1).
+#define DGMG_NP_LIST(X) X(2) X(3) X(4) X(5) X(7) X(9) X(13) X(17) X(33)
 // Transfer pairs (NP fine, NP coarse) for P -> floor(P / 2).
-#define DGMG_XFER_LIST(X) X(3, 2) X(4, 2) X(5, 3) X(7, 4) X(9, 5) X(13, 7) X(17, 9)
+#define DGMG_XFER_LIST(X) X(3, 2) X(4, 2) X(5, 3) X(7, 4) X(9, 5) X(13, 7) X(17, 9) X(33, 17)
+// 3D elements with NP = BIG_NP and patch tiles beyond LDS use kernels_big.hpp.
+constexpr size_t LDS_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 // Patch tiles (NA, NL): element-centred (n, n) with n = NP + 2 N_O and
 // face-centred (2P, NP + 2 N_O) for the overlaps N_O the level rules produce
 // (and N_O = 0, 1 for the zero-overlap variants).
@@ -17,14 +20,18 @@ namespace dgmg {
   X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 7) X(9, 9) X(11, 11) X(13, 13) X(15, 15) X(17, 17) \
   X(19, 19) X(21, 21) X(23, 23) X(4, 3) X(4, 5) X(6, 4) X(8, 5) X(8, 7) X(8, 9) X(12, 7)  \
   X(12, 9) X(12, 11) X(16, 9) X(16, 11) X(16, 13) X(16, 15) X(24, 13) X(24, 17) X(24, 19) \
-  X(32, 17) X(32, 21) X(32, 23)
+  X(32, 17) X(32, 21) X(32, 23) X(33, 33) X(35, 35) X(43, 43) X(64, 33) X(64, 35) X(64, 43)
 
 template <class T, int DIM>
 int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
                         int* nblk, hipStream_t s) {
   switch (L.NP) {
-#define DGMG_CASE(NP) \
-  case NP: return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
+#define DGMG_CASE(NP)                                                              \
+  case NP:                                                                         \
+    if constexpr (DIM == 3 && NP == BIG_NP)                                        \
+      return apply_big_launch<T, NP>(L, mode, x, f, y, part, nblk, s);             \
+    else                                                                           \
+      return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
     DGMG_NP_LIST(DGMG_CASE)
 #undef DGMG_CASE
     default: return -4;
@@ -43,8 +50,13 @@ bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
 template <class T, int DIM>
 int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx,
                       int npy, int npz, int waves, hipStream_t s) {
-#define DGMG_CASE(A, B) \
-  if (NA == A && NL == B) return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, s);
+#define DGMG_CASE(A, B)                                                                   \
+  if (NA == A && NL == B) {                                                               \
+    if constexpr (DIM == 3 && fdm_shmem<T, A, B, DIM>() + 4096 > LDS_BYTES)               \
+      return fdm_big_launch<T, A, B>(L, nd, r, out, npx, npy, npz, s);                    \
+    else                                                                                  \
+      return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, s);          \
+  }
   DGMG_FDM_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;
@@ -63,12 +75,16 @@ int Kern<T, DIM>::combine(const LevelDev<T>& L, int nd, int NA, int NL, const T*
 }
 
 template <class T, int DIM>
-int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out,
+int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, T* tmp,
                            hipStream_t s) {
-#define DGMG_CASE(F, C)                                                                          \
-  if (Lf.NP == F && Lf.NPc == C)                                                                 \
-    return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, Lf.active, s) \
-                     : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, Lf.active, s);
+#define DGMG_CASE(F, C)                                                                                \
+  if (Lf.NP == F && Lf.NPc == C) {                                                                     \
+    if constexpr (DIM == 3 && F == BIG_NP)                                                             \
+      return transfer_big_launch<T, F, C>(Lf.J, Lf.n_elem, restrict_, in, out, tmp, Lf.active, s);    \
+    else                                                                                               \
+      return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, Lf.active, s) \
+                       : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, Lf.active, s); \
+  }
   DGMG_XFER_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;

@@ -661,7 +661,8 @@ struct Kern {
   static bool fdm_supported(int NA, int NL);
   static int combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, hipStream_t s);
-  static int transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, hipStream_t s);
+  // tmp: scratch of transfer_big_scratch(n_elem, NP, NPc) elements (3D levels with NP = 33 only)
+  static int transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, T* tmp, hipStream_t s);
 };
 
 }  // namespace dgmg

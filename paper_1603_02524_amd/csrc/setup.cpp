@@ -403,4 +403,76 @@ std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels) 
   return std::string();
 }
 
+int face_count(const std::vector<LevelHost>& levels) {
+  int c = 0;
+  for (size_t l = 1; l < levels.size(); ++l)
+    for (int d = 0; d < levels[l].dim; ++d) c += levels[l].dir[d].nf;
+  return c;
+}
+
+void face_features(const std::vector<LevelHost>& levels, std::vector<double>& X) {
+  X.clear();
+  for (size_t l = 1; l < levels.size(); ++l) {
+    const LevelHost& lv = levels[l];
+    double mlog[3] = {0, 0, 0};
+    for (int d = 0; d < lv.dim; ++d) {
+      for (double h : lv.dir[d].dx) mlog[d] += std::log2(h);
+      mlog[d] /= (double)lv.dir[d].dx.size();
+    }
+    for (int d = 0; d < lv.dim; ++d) {
+      double lat = 0;
+      for (int e = 0; e < lv.dim; ++e)
+        if (e != d) lat += mlog[e];
+      lat /= (double)(lv.dim - 1);
+      const Dir1D& dd = lv.dir[d];
+      for (int f = 0; f < dd.nf; ++f) {
+        int left = f - 1, right = f;
+        bool boundary = false;
+        if (dd.periodic) {
+          left = (left + dd.N) % dd.N;
+          right = right % dd.N;
+        } else {
+          if (left < 0) left = 0, boundary = true;
+          if (right >= dd.N) right = dd.N - 1, boundary = true;
+        }
+        X.push_back(lv.P / 32.0);
+        X.push_back((std::log2(dd.dx[left]) - lat) / 5.0);
+        X.push_back((std::log2(dd.dx[right]) - lat) / 5.0);
+        X.push_back(boundary ? 1.0 : 0.0);
+        X.push_back(lv.dim - 2.0);
+        X.push_back(lv.NO / (double)lv.NP);
+      }
+    }
+  }
+}
+
+void fc_weights_param(const LevelHost& lv, int d, int kind, const double* theta, const double* omega,
+                      std::vector<double>& w) {
+  const Dir1D& dd = lv.dir[d];
+  const int NP = lv.NP, a = dd.n_fc, G = dd.N * NP;
+  std::vector<double> eta, rho;
+  gll_points(lv.P, eta, rho);
+  w.assign((size_t)dd.nf * a, 0.0);
+  std::vector<double> total(G, 0.0);
+  std::vector<int> gi((size_t)dd.nf * a, -1);
+  for (int f = 0; f < dd.nf; ++f)
+    for (int t = 0; t < a; ++t) {
+      const int g = (f - 1) * NP + 1 + t;
+      int gw = g;
+      if (dd.periodic) gw = ((g % G) + G) % G;
+      else if (g < 0 || g >= G) continue;
+      const int mm = (int)std::floor((double)g / NP), i = g - mm * NP;
+      const double xf = (mm == f - 1) ? eta[i] - 1.0 : eta[i] + 1.0;
+      const double wt = 0.5 * (1.0 + phi((1.0 - std::fabs(xf)) / theta[f], kind));
+      w[(size_t)f * a + t] = wt;
+      gi[(size_t)f * a + t] = gw;
+      total[gw] += wt;
+    }
+  for (int f = 0; f < dd.nf; ++f)
+    for (int t = 0; t < a; ++t) {
+      const int gw = gi[(size_t)f * a + t];
+      if (gw >= 0) w[(size_t)f * a + t] *= omega[f] / total[gw];
+    }
+}
+
 }  // namespace dgmg

@@ -74,6 +74,25 @@ std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels);
 void gll_points(int P, std::vector<double>& eta, std::vector<double>& rho);
 void gll_diff(int P, const std::vector<double>& eta, std::vector<double>& D);
 int overlap_rule(int P_l, int overlap);
+// Learned-weight variant of the face-centred smoother (not in the paper).
+// Faces are enumerated level by level (l = 1 .. L), then by normal direction d,
+// then by face index f = 0 .. nf_d - 1.
+constexpr int FACE_FEATURES = 6;
+int face_count(const std::vector<LevelHost>& levels);
+// Features per face, FACE_FEATURES each: P_l / 32, log2(dx_left / h_lat) / 5,
+// log2(dx_right / h_lat) / 5, 1 on a Dirichlet boundary face else 0, dim - 2,
+// N_O,l / (P_l + 1).  h_lat is the geometric mean of the element sizes of the
+// other directions; a missing neighbour element at a boundary face is replaced
+// by the existing one.
+void face_features(const std::vector<LevelHost>& levels, std::vector<double>& X);
+// Normal weights of the face-centred patches of direction d on one level with a
+// transition width theta_f and a damping omega_f per face:
+//   w_f = omega_f * wt_f / (sum of wt_f' over the faces whose patch covers the node),
+//   wt_f = 1/2 [1 + phi((1 - |xi_F|) / theta_f)]   (theta = 1: the weight of Sec. 3.1).
+// Layout as Dir1D::w_fc (nf * n_fc, padding positions 0).
+void fc_weights_param(const LevelHost& lv, int d, int kind, const double* theta, const double* omega,
+                      std::vector<double>& w);
+
 // Symmetric eigen-decomposition by the cyclic Jacobi method: A (n*n, row-major,
 // destroyed) -> eigenvalues lam, eigenvectors as columns of V (row-major).
 void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgmg.so")
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, FELLBACK = 0, 1, 2
 F64, F32 = 0, 1
 
 _FLUX = {"ip": 0, "ldg": 1}
@@ -55,6 +55,7 @@ SIGNATURES = [
     ("dgmg_apply", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     ("dgmg_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int]),
     ("dgmg_smooth", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int]),
+    ("dgmg_sweep", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int]),
     ("dgmg_restrict", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     ("dgmg_prolong", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     ("dgmg_coarse_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
@@ -70,6 +71,18 @@ SIGNATURES = [
     ("dgmg_tune_set", c_int, [c_void_p, c_int, c_int, c_int]),
     ("dgmg_destroy", None, [c_void_p]),
     ("dgmg_last_error", ctypes.c_char_p, [c_void_p]),
+    ("dgmg_face_count", c_int, [c_void_p]),
+    ("dgmg_face_features", c_int, [c_void_p, POINTER(ctypes.c_float)]),
+    ("dgmg_set_face_params", c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    ("dgmg_get_face_params", c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    ("dgmg_mlp_param_count", c_int, []),
+    ("dgmg_mlp_forward", c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    ("dgmg_mlp_backward", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p]),
+    ("dgmg_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
+    ("dgmg_mlp_work_bytes", c_int, [c_void_p, POINTER(c_size_t)]),
+    ("dgmg_apply_mlp", c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, POINTER(c_double)]),
     ("dgmg_batch_setup", c_int, [c_int, POINTER(DgmgGrid), POINTER(DgmgOpts), POINTER(c_void_p)]),
     ("dgmg_batch_workspace_bytes", c_int, [c_void_p, POINTER(c_size_t)]),
     ("dgmg_batch_bind_workspace", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -243,6 +256,12 @@ class Solver:
                                          self._dtype_code(u)))
         return u
 
+    def sweep(self, level, u, f, normal=-1):
+        """One additive Schwarz sweep in place on u (normal -1: element-centred)."""
+        self._check(self.lib.dgmg_sweep(self.h, level, self._ptr(u), self._ptr(f), int(normal),
+                                        self._dtype_code(u)))
+        return u
+
     def restrict(self, level, r_fine, f_coarse=None):
         if f_coarse is None:
             f_coarse = self.torch.empty(self.n_dof(level - 1), dtype=r_fine.dtype, device=self.device)
@@ -305,6 +324,120 @@ class Solver:
         self._check(self.lib.dgmg_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
                                               ctypes.byref(by)))
         return {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}
+
+    # ------------------------------------------------------------------ learned face weights
+    def face_count(self):
+        return self._check(self.lib.dgmg_face_count(self.h), allow=range(0, 1 << 30))
+
+    def face_features(self):
+        return _face_features(self.lib, self.h)
+
+    def set_face_params(self, theta=None, omega=None):
+        """Impose (theta, omega) per face (host arrays), or restore the fixed weights."""
+        if theta is None:
+            self._check(self.lib.dgmg_set_face_params(self.h, None, None))
+            return
+        n = self.face_count()
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n)
+        om = np.ascontiguousarray(omega, dtype=np.float64).reshape(n)
+        self._check(self.lib.dgmg_set_face_params(self.h, th.ctypes.data_as(POINTER(c_double)),
+                                                  om.ctypes.data_as(POINTER(c_double))))
+
+    def face_params(self):
+        n = self.face_count()
+        th, om = np.zeros(n), np.zeros(n)
+        rc = self.lib.dgmg_get_face_params(self.h, th.ctypes.data_as(POINTER(c_double)),
+                                           om.ctypes.data_as(POINTER(c_double)))
+        self._check(rc, allow=(0, 1))
+        return th, om, bool(rc)
+
+    def apply_mlp(self, params, probe_iters=3):
+        """Learned weights from the MLP (FP32 device params) with the probe fallback.
+
+        Returns (kept, ratio_learned, ratio_fixed)."""
+        nb = c_size_t()
+        self._check(self.lib.dgmg_mlp_work_bytes(self.h, ctypes.byref(nb)))
+        work = self.torch.empty(int(nb.value) + 256, dtype=self.torch.uint8, device=self.device)
+        aligned = (work.data_ptr() + 255) // 256 * 256
+        ratios = (c_double * 2)()
+        rc = self._check(self.lib.dgmg_apply_mlp(self.h, self._ptr(params), c_void_p(aligned), int(nb.value),
+                                                 int(probe_iters), ratios), allow=(0, FELLBACK))
+        return rc == 0, ratios[0], ratios[1]
+
+
+def _face_features(lib, h):
+    n = lib.dgmg_face_count(h)
+    if n < 0:
+        raise DgmgError(n, "face count")
+    X = np.zeros((n, MLP_IN), dtype=np.float32)
+    rc = lib.dgmg_face_features(h, X.ctypes.data_as(POINTER(ctypes.c_float)))
+    if rc:
+        raise DgmgError(rc, "face features")
+    return X
+
+
+def face_features(grid, method):
+    """Per-face MLP features of a problem (host only: no device needed)."""
+    lib = load_library()
+    h, keep = setup_handle(grid, method)
+    try:
+        return _face_features(lib, h)
+    finally:
+        lib.dgmg_destroy(h)
+
+
+MLP_IN, MLP_HIDDEN, MLP_OUT = 6, 64, 2
+
+
+def mlp_param_count():
+    return load_library().dgmg_mlp_param_count()
+
+
+def _dptr(t):
+    if not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("MLP arrays must be contiguous device tensors")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    import torch
+    return c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_forward(params, X):
+    """Y [B][OUT] and the hidden activations [B][2 HIDDEN] (float32 device tensors)."""
+    import torch
+    lib = load_library()
+    B = X.shape[0]
+    Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=X.device)
+    work = torch.empty((B, 2 * MLP_HIDDEN), dtype=torch.float32, device=X.device)
+    rc = lib.dgmg_mlp_forward(_dptr(params), _dptr(X), B, _dptr(Y), _dptr(work), _stream(X))
+    if rc:
+        raise DgmgError(rc, "mlp forward")
+    return Y, work
+
+
+def mlp_backward(params, X, T, Y, work):
+    """Gradient of (1/B) sum (Y - T)^2 with respect to the parameters."""
+    import torch
+    lib = load_library()
+    B = X.shape[0]
+    grad = torch.empty_like(params)
+    scratch = torch.empty(B * (2 * MLP_HIDDEN + MLP_OUT), dtype=torch.float32, device=X.device)
+    rc = lib.dgmg_mlp_backward(_dptr(params), _dptr(X), _dptr(T), B, _dptr(Y), _dptr(work), _dptr(grad),
+                               _dptr(scratch), _stream(X))
+    if rc:
+        raise DgmgError(rc, "mlp backward")
+    return grad
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One in-place Adam step on params (m, v: moment tensors, updated in place)."""
+    lib = load_library()
+    rc = lib.dgmg_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), params.numel(), int(t), lr, b1, b2,
+                           eps, _stream(params))
+    if rc:
+        raise DgmgError(rc, "mlp adam")
 
 
 def _stats_dict(st, rc):

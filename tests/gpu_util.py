@@ -31,6 +31,10 @@ CASES = [
     ("3d_dir_ip_p8_ea0", dict(dim=3, n=(3, 2, 2), seed=8), dict(P=8, smoother="EA", overlap="zero")),
     ("3d_dir_ip_p12_fa", dict(dim=3, n=(2, 2, 1), seed=9), dict(P=12, smoother="FA")),
     ("3d_dir_ip_p16_ea", dict(dim=3, n=(2, 1, 2), seed=10), dict(P=16, smoother="EA")),
+    ("3d_dir_ip_p16_fa", dict(dim=3, n=(1, 2, 2), seed=13), dict(P=16, smoother="FA")),
+    # P = 32: 3D elements and patch tiles beyond LDS (two-stage transfers, three-stage patch solves)
+    ("3d_dir_ip_p32_fa", dict(dim=3, n=(2, 1, 2), seed=11), dict(P=32, smoother="FA")),
+    ("3d_dir_ip_p32_ea", dict(dim=3, n=(1, 2, 2), seed=12), dict(P=32, smoother="EA")),
 ]
 
 

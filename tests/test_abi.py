@@ -143,3 +143,20 @@ def test_batch_layout_host_side():
             assert off[i + 1] - off[i] == g.n_dof(m.P)
     finally:
         lib.dgmg_batch_destroy(b)
+
+
+@pytest.mark.parametrize("name", ["c1", "c5", "periodic"])
+def test_face_features_match_oracle(name):
+    """Per-face MLP features computed by the library's host setup equal the oracle's."""
+    from oracle import learned
+    from paper_1603_02524_amd import dgmg
+    if name == "c1":
+        w = synth.with_method(synth.c1_poisson2d_p4(), smoother="FA")
+    elif name == "c5":
+        w = synth.c5_poisson3d_p32(n=3)
+    else:
+        w = synth.paper_periodic_2d(8, n=4, ar=4, smoother="FA")
+    X = dgmg.face_features(w.grid, w.method)
+    ref = learned.face_features(w.grid, w.method)
+    assert X.shape == ref.shape
+    assert np.allclose(X, ref, rtol=0, atol=2e-7)

@@ -139,3 +139,24 @@ def test_zero_residual_gives_zero_correction():
     g, A, lev = _level(2, 3, 4, False, "FA", 1)
     u = np.random.default_rng(3).standard_normal(A.shape[0])
     assert np.allclose(lev.smooth(u, A @ u, 2), u, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,periodic,smoother,P", [(2, True, "EA", 3), (3, False, "FA", 4), (3, True, "FA", 2),
+                                                     (2, False, "FA", 6)])
+def test_sampled_sweep_equals_full_sweep(dim, periodic, smoother, P):
+    """sweep_at (covering patches only) reproduces the full sweep at sampled nodes."""
+    from oracle.multigrid import Hierarchy
+    rng = np.random.default_rng(dim * 10 + P)
+    n = (3, 4, 3)[:dim]
+    g = synth.Grid(dim, tuple(rng.uniform(0.5, 1.5, n[d]) for d in range(dim)), (periodic,) * dim)
+    m = synth.Method(P=P, smoother=smoother)
+    H = Hierarchy(g, m, assemble=False, coarse=False)
+    sm = H.levels[H.L].smoother
+    N = g.n_dof(P)
+    u = rng.standard_normal(N)
+    f = rng.standard_normal(N)
+    nodes = np.concatenate([[0, N - 1], rng.choice(N, 25, replace=False)])
+    for normal in ([-1] if smoother == "EA" else list(range(dim))):
+        full = sm.sweep(u, f, normal)
+        part = sm.sweep_at(u, f, normal, nodes)
+        assert np.allclose(part, full[nodes], rtol=0, atol=1e-12 * np.abs(full).max()), normal
