@@ -28,6 +28,37 @@ METRIC = "DoF/s to 1e-10 rel. residual (PCG+pMG), smoother HBM GB/s; mixed vs FP
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE), scaled by the same counters on a plain copy of
+# known size (bench.py --copy-calibration); the summary with commands is in
+# profiles/.  Valid only for the kernel source it was measured on: the hash of
+# the kernel headers is compared at run time and the figure dropped on change.
+TRAFFIC = {"bytes_per_launch": None, "kernel_src_sha256": None, "profile": None}
+KERNEL_SOURCES = ("paper_1603_02524_amd/csrc/kernels.hpp", "paper_1603_02524_amd/csrc/dispatch.hpp")
+
+
+def _kernel_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _copy_calibration(mb, reps=5):
+    """Plain device copies of a known size (the calibration kernel of the PMC runs)."""
+    import torch
+    n = mb * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
+                                           "copies": reps}}), flush=True)
+
 
 def _workload(name):
     import synth
@@ -99,11 +130,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run plain device copies of MB MiB (PMC calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the solver "
               "runs on a single MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
         raise SystemExit(2)
+
+    if args.copy_calibration:
+        _copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -135,8 +172,11 @@ def main():
     k_flops = kt["flops"] / max(kt["launches"], 1)
     k_bytes = kt["bytes"] / max(kt["launches"], 1)
     achieved = k_flops / (k_ms * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC["bytes_per_launch"] and TRAFFIC["kernel_src_sha256"] == _kernel_src_hash():
+        traffic = TRAFFIC["bytes_per_launch"]
     roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
             "kernel": "fdm_kernel<double,3,16,13> (face-centred patch solve, P=8, N_O=2)",
             "avg_ms": k_ms, "launches": kt["launches"], "flops_per_launch": k_flops,
             "alg_bytes_per_launch": k_bytes, "alg_GBps": k_bytes / (k_ms * 1e-3) / 1e9}

@@ -350,12 +350,40 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restri
   }
 }
 
-template <class T, int DIM, int NA, int NL>
-__global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T* __restrict__ r,
-                                                  T* __restrict__ out, int npx, int npy, int npz) {
-  constexpr int TS = fdm_tile<NA, NL, DIM>();
-  constexpr int NAP = fdm_pitch<NA>();
+// Tile geometry of one sweep kind, all compile-time: ND = normal direction of a
+// face-centred patch (-1: element-centred).  Grid-natural order has direction 0
+// fastest with lengths L0, L1, L2; the LDS tile keeps the normal direction
+// fastest: tile[(l2 NL + l1) NAP + a].
+template <int DIM, int ND, int NA, int NL>
+struct FdmShape {
+  static constexpr int L0 = ND == 0 ? NA : NL;
+  static constexpr int L1 = ND == 1 ? NA : NL;
+  static constexpr int L2 = DIM == 3 ? (ND == 2 ? NA : NL) : 1;
+  static constexpr int TS = L0 * L1 * L2;
+  static constexpr int NAP = fdm_pitch<NA>();
+  // grid direction of tile dimension t (t = 0: the normal / fastest one)
+  static constexpr int gd(int t) {
+    return ND <= 0 ? t : (t == 0 ? ND : (t <= ND ? t - 1 : t));
+  }
+  static __device__ __forceinline__ int tpos(int o0, int o1, int o2) {
+    const int o[3] = {o0, o1, o2};
+    return ((DIM == 3 ? o[gd(2)] * NL : 0) + o[gd(1)]) * NAP + o[gd(0)];
+  }
+  static __device__ __forceinline__ void split(int q, int& o0, int& o1, int& o2) {
+    o0 = q % L0;
+    const int rest = q / L0;
+    o1 = DIM == 3 ? rest % L1 : rest;
+    o2 = DIM == 3 ? rest / L1 : 0;
+  }
+};
+
+template <class T, int DIM, int NA, int NL, int ND>
+__global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
+                                                  int npx, int npy, int npz) {
+  using S = FdmShape<DIM, ND, NA, NL>;
+  constexpr int TS = S::TS;
   constexpr int NMAX = imax(NA, NL);
+  constexpr int GU = 4;  // elements gathered per thread before their LDS stores (loads in flight)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
   __shared__ int64_t goff[3][NMAX];
@@ -370,28 +398,19 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   p[0] = pid % npx;
   p[1] = (pid / npx) % npy;
   p[2] = DIM == 3 ? pid / (npx * npy) : 0;
-  int gd[3];  // tile dimension t -> grid direction
-  if (nd < 0) {
-    gd[0] = 0; gd[1] = 1; gd[2] = 2;
-  } else {
-    gd[0] = nd;
-    int q = 1;
-    for (int d = 0; d < DIM; ++d)
-      if (d != nd) gd[q++] = d;
-  }
-  int len[3] = {1, 1, 1};
-  for (int d = 0; d < DIM; ++d) len[d] = (d == nd) ? NA : NL;
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   const int64_t est[3] = {(int64_t)NE, (int64_t)N1 * NE, (int64_t)N1 * N2 * NE};
   const int nst[3] = {1, NP, NP * NP};
+#pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const DirDev<T>& dd = L.dir[d];
-    const bool fc = d == nd;
+    const bool fc = d == ND;
+    const int len = fc ? NA : NL;
     const int start = fc ? (p[d] - 1) * NP + 1 : p[d] * NP - L.NO;
     const int G = dd.N * NP;
     const T* w = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
     const T* lam = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
-    for (int o = tid; o < len[d]; o += nth) {
+    for (int o = tid; o < len; o += nth) {
       int g = start + o;
       int64_t off = -1;
       if (dd.periodic) g = ((g % G) + G) % G;
@@ -408,10 +427,11 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   // backward u_k = sum_j S_kj t_j uses S^T (both row-major)
   const T* fwd[3] = {nullptr, nullptr, nullptr};
   const T* bwd[3] = {nullptr, nullptr, nullptr};
+#pragma unroll
   for (int t = 0; t < DIM; ++t) {
-    const int d = gd[t];
+    const int d = S::gd(t);
     const DirDev<T>& dd = L.dir[d];
-    if (d == nd) {
+    if (d == ND) {
       fwd[t] = dd.S_fc + (int64_t)p[d] * NA * NA;
       bwd[t] = dd.ST_fc + (int64_t)p[d] * NA * NA;
     } else {
@@ -420,22 +440,26 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
     }
   }
   __syncthreads();
-  // gather R_s r (grid-natural order: coalesced global reads)
-  for (int q = tid; q < TS; q += nth) {
-    int o[3];
-    o[0] = q % len[0];
-    const int rest = q / len[0];
-    o[1] = DIM == 3 ? rest % len[1] : rest;
-    o[2] = DIM == 3 ? rest / len[1] : 0;
-    int64_t off = 0;
-    bool ok = true;
-    for (int d = 0; d < DIM; ++d) {
-      const int64_t g = goff[d][o[d]];
-      ok = ok && g >= 0;
-      off += g;
+  // gather R_s r in grid-natural order (coalesced global reads); GU loads are
+  // issued before their LDS stores; positions outside a Dirichlet domain read
+  // r[0] and store 0
+  for (int q0 = tid; q0 < TS; q0 += GU * nth) {
+    T v[GU];
+    int pos[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int q = q0 + u * nth;
+      int o0, o1, o2;
+      S::split(q < TS ? q : 0, o0, o1, o2);
+      const int64_t g0 = goff[0][o0], g1 = goff[1][o1], g2 = DIM == 3 ? goff[2][o2] : 0;
+      const bool ok = q < TS && g0 >= 0 && g1 >= 0 && g2 >= 0;
+      v[u] = r[ok ? g0 + g1 + g2 : 0];
+      v[u] = ok ? v[u] : T(0);
+      pos[u] = q < TS ? S::tpos(o0, o1, o2) : -1;
     }
-    const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
-    tile[(l2 * NL + l1) * NAP + a] = ok ? r[off] : T(0);
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+      if (pos[u] >= 0) tile[pos[u]] = v[u];
   }
   __syncthreads();
   fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
@@ -450,9 +474,9 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   for (int q = tid; q < TS; q += nth) {
     const int a = q % NA, rest = q / NA;
     const int l1 = DIM == 3 ? rest % NL : rest, l2 = DIM == 3 ? rest / NL : 0;
-    T den = lv[gd[0]][a] + lv[gd[1]][l1];
-    if (DIM == 3) den += lv[gd[2]][l2];
-    const int idx = (l2 * NL + l1) * NAP + a;
+    T den = lv[S::gd(0)][a] + lv[S::gd(1)][l1];
+    if (DIM == 3) den += lv[S::gd(2)][l2];
+    const int idx = (l2 * NL + l1) * S::NAP + a;
     tile[idx] = tile[idx] / den;
   }
   __syncthreads();
@@ -467,16 +491,23 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, int nd, const T
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
   for (int q = tid; q < TS; q += nth) {
-    int o[3];
-    o[0] = q % len[0];
-    const int rest = q / len[0];
-    o[1] = DIM == 3 ? rest % len[1] : rest;
-    o[2] = DIM == 3 ? rest / len[1] : 0;
-    const int a = o[gd[0]], l1 = o[gd[1]], l2 = DIM == 3 ? o[gd[2]] : 0;
-    T w = wv[0][o[0]] * wv[1][o[1]];
-    if (DIM == 3) w *= wv[2][o[2]];
-    dst[q] = w * tile[(l2 * NL + l1) * NAP + a];
+    int o0, o1, o2;
+    S::split(q, o0, o1, o2);
+    T w = wv[0][o0] * wv[1][o1];
+    if (DIM == 3) w *= wv[2][o2];
+    dst[q] = w * tile[S::tpos(o0, o1, o2)];
   }
+}
+
+template <class T, int DIM, int NA, int NL, int ND>
+void fdm_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, int npz, int th, size_t shm,
+                   hipStream_t s) {
+  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL, ND>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL, ND>), dim3(xcd_grid(npatch)), dim3(th), shm, s, L, r, out, npx, npy,
+                     npz);
 }
 
 // waves: wavefronts per block (1, 2 or 4; 0 = default), the shape the autotuner picks.
@@ -484,13 +515,18 @@ template <class T, int DIM, int NA, int NL>
 int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
                  int waves, hipStream_t s) {
   constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
-  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
-  if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   const int th = (waves >= 1 && waves <= 4) ? 64 * waves : fdm_threads<NA, NL, DIM>();
-  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL>), dim3(xcd_grid(npatch)), dim3(th), shm, s, L, nd, r,
-                     out, npx, npy, npz);
+  if (nd < 0) {
+    if constexpr (NA == NL) {
+      fdm_launch_nd<T, DIM, NA, NL, -1>(L, r, out, npx, npy, npz, th, shm, s);
+      return 0;
+    }
+    return -4;
+  }
+  if (nd == 0) fdm_launch_nd<T, DIM, NA, NL, 0>(L, r, out, npx, npy, npz, th, shm, s);
+  else if (nd == 1) fdm_launch_nd<T, DIM, NA, NL, 1>(L, r, out, npx, npy, npz, th, shm, s);
+  else if constexpr (DIM == 3) fdm_launch_nd<T, DIM, NA, NL, 2>(L, r, out, npx, npy, npz, th, shm, s);
+  else return -4;
   return 0;
 }
 

@@ -86,13 +86,13 @@ def params_to_outputs(theta, omega):
 
 # ---------------------------------------------------------------------- data
 def training_problems(seed=11, count=24):
-    """3D Dirichlet FA problems, P in {4, 8, 16}, aspect ratios 1 .. 32."""
+    """3D Dirichlet FA problems, P in {4, 8, 16} on 8^3 / 8^3 / 6^3 elements, aspect ratios 1 .. 32."""
     import synth
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
         P = (4, 8, 16)[k % 3]
-        n = 4 if P < 16 else 3
+        n = 8 if P < 16 else 6
         max_log2 = (0.0, 2.0, 3.5, 5.0)[(k // 3) % 4]
         dx = tuple(synth.random_spacing(rng, n, max_log2, 1.0) for _ in range(3))
         g = synth.Grid(3, dx, (False, False, False))

@@ -119,3 +119,31 @@ def test_fullsize_solve_true_residual(big):
     res = np.linalg.norm(fl - H.apply(H.L, xl)) / np.linalg.norm(fl)
     print(f"  {name}: {st['iterations']} iterations, rho {st['rho']:.4f}, true residual {res:.2e}")
     assert st["converged"] and res < 2e-10
+
+
+def test_fullsize_learned_weights_no_worse(big):
+    """Learned face weights (shipped network, probe fallback) on the full workload:
+    the solve still reaches the true residual and takes no more iterations."""
+    import os
+    from paper_1603_02524_amd import learn
+    name, w, S, H = big
+    g, m = w.grid, w.method
+    if m.smoother != "FA" or not os.path.exists(learn.DEFAULT_PARAMS):
+        pytest.skip("learned weights need the face-centred smoother and a shipped network")
+    n = g.n_dof(m.P)
+    f = _dev(synth.rhs_uniform(w.seed, n))
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    S.set_face_params(None)
+    fixed = S.solve(f, x, tol=1e-10)
+    params = torch.tensor(learn.load_params(), device="cuda")
+    kept, rl, rf = S.apply_mlp(params, probe_iters=4)
+    x.zero_()
+    st = S.solve(f, x, tol=1e-10)
+    xl = to_lex(_host(x), g, m.P)
+    fl = to_lex(_host(f), g, m.P)
+    res = np.linalg.norm(fl - H.apply(H.L, xl)) / np.linalg.norm(fl)
+    S.set_face_params(None)
+    print(f"  {name} learned kept={kept} probe {rl:.3e} vs {rf:.3e}: {st['iterations']} vs {fixed['iterations']} "
+          f"iterations, rho {st['rho']:.4f} vs {fixed['rho']:.4f}, true residual {res:.2e}")
+    assert st["converged"] and res < 2e-10
+    assert st["iterations"] <= fixed["iterations"]

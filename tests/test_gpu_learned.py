@@ -225,7 +225,7 @@ def test_neutral_network_equals_fixed_weights():
 
 
 @pytest.mark.skipif(not os.path.exists(learn.DEFAULT_PARAMS), reason="no trained network shipped")
-@pytest.mark.parametrize("seed,n,P", [(55, 4, 8), (56, 3, 16), (57, 4, 4)])
+@pytest.mark.parametrize("seed,n,P", [(55, 8, 8), (56, 5, 16), (57, 8, 4)])
 def test_shipped_network_is_no_worse_than_fixed(seed, n, P):
     """Learned weights (after the probe) never take more MGCG iterations than the fixed ones."""
     g, m = _c5_like(seed, n, P)
