@@ -33,7 +33,9 @@ HBM_PEAK_GBPS = 8000.0
 # known size (bench.py --copy-calibration); the summary with commands is in
 # profiles/.  Valid only for the kernel source it was measured on: the hash of
 # the kernel headers is compared at run time and the figure dropped on change.
-TRAFFIC = {"bytes_per_launch": None, "kernel_src_sha256": None, "profile": None}
+TRAFFIC = {"bytes_per_launch": 133.6e6,
+           "kernel_src_sha256": "9e7f121267dbefa290db359a1233bd798f3378f23619e7b370a778a7c57f96c6",
+           "profile": "profiles/fdm_p8_c2_fp64_pmc_traffic.md"}
 KERNEL_SOURCES = ("paper_1603_02524_amd/csrc/kernels.hpp", "paper_1603_02524_amd/csrc/dispatch.hpp")
 
 
@@ -129,6 +131,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB MiB (PMC calibration) and exit")
@@ -156,6 +159,12 @@ def main():
     rhs_np = synth.rhs_uniform(w.seed, n)
     rhs = torch.tensor(rhs_np, dtype=torch.float64, device="cuda")
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    if not args.no_autotune:
+        # patch-solve block shapes per (level, sweep kind); bitwise-neutral, outside the timed region
+        _log("autotuning patch-solve block shapes")
+        tuning = S.autotune()
+    else:
+        tuning = {}
     _log("timing FP64 solves")
     sec, st, kt = _time_solves(S, rhs, x, w.tol, args.warmup, args.steps, timing=True)
     _log(f"FP64: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
@@ -187,13 +196,16 @@ def main():
            "config": {"workload": w.name, "elements": list(g.n), "P": m.P, "n_dof": n,
                       "flux": m.flux, "smoother": f"{m.smoother}_l", "vcycle": "V(1,1)",
                       "precision": m.precision, "tol": w.tol, "seed": w.seed,
-                      "iterations": st["iterations"], "true_rel_residual": true_rel},
+                      "iterations": st["iterations"], "true_rel_residual": true_rel,
+                      "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())}},
            "roofline": roof}
 
     if not args.no_mixed:
         _log("timing mixed-precision solves")
         wm = synth.with_method(w, precision="mixed")
         Sm = dgmg.Solver(wm.grid, wm.method, max_iter=200)
+        if not args.no_autotune:
+            Sm.autotune()
         xm = torch.zeros(n, dtype=torch.float64, device="cuda")
         secm, stm, _ = _time_solves(Sm, rhs, xm, w.tol, args.warmup, args.steps, timing=False)
         rm = Sm.residual(Sm.num_levels - 1, rhs, xm)
