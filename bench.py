@@ -197,7 +197,8 @@ def main():
                       "flux": m.flux, "smoother": f"{m.smoother}_l", "vcycle": "V(1,1)",
                       "precision": m.precision, "tol": w.tol, "seed": w.seed,
                       "iterations": st["iterations"], "true_rel_residual": true_rel,
-                      "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())}},
+                      "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())},
+                      "autotuned_sweep_us": {f"l{l}k{k}": round(v[1] * 1e3, 2) for (l, k), v in sorted(tuning.items())}},
            "roofline": roof}
 
     if not args.no_mixed:

@@ -221,7 +221,7 @@ int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double
  * stream or a tuning choice changes. */
 int dgmg_use_graphs(dgmg_handle* h, int enable);
 
-/* Autotuner: time the patch-solve block shapes (1, 2 or 4 wavefronts per
+/* Autotuner: time the patch-solve block shapes (1, 2, 4 or 8 wavefronts per
  * patch) of every smoothing sweep on the bound workspace and keep the fastest
  * (synchronises; results are bitwise independent of the choice).
  * dgmg_tune_get/set read or impose the choice for (level >= 1, kind), kind

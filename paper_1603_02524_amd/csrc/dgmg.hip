@@ -501,12 +501,15 @@ int k_fdm(dgmg_handle* h, int l, int nd, const T* r, int waves) {
   return DGMG_OK;
 }
 
+// One additive sweep.  u_zero: the caller guarantees u == 0, so the residual
+// f - A u is f itself and the patch solves read f directly.
 template <class T>
-int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r) {
+int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero = false) {
   const LevelDev<T>& L = LD<T>(h, l);
   const LevelHost& lv = h->lv[l];
-  int rc = k_apply<T>(h, l, 1, u, f, r, nullptr, nullptr);
+  int rc = u_zero ? DGMG_OK : k_apply<T>(h, l, 1, u, f, r, nullptr, nullptr);
   if (rc) return rc;
+  const T* res = u_zero ? f : r;
   int np[3], NA, NL;
   sweep_shape(lv, nd, np, NA, NL);
   const int kind = nd < 0 ? 3 : nd;
@@ -517,7 +520,7 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r) {
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, h->stream);
   }
-  rc = k_fdm<T>(h, l, nd, r, h->waves[l][kind]);
+  rc = k_fdm<T>(h, l, nd, res, h->waves[l][kind]);
   if (rc) return rc;
   if (timed) {
     (void)hipEventRecord(e1, h->stream);
@@ -541,15 +544,17 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r) {
   return check_hip(h, "combine");
 }
 
+// `steps` smoothing steps (EA: one sweep; FA: one sweep per direction).
+// u_zero: u == 0 on entry (the first sweep then skips its residual apply).
 template <class T>
-int k_smooth(dgmg_handle* h, int l, T* u, const T* f, int steps, T* r) {
+int k_smooth(dgmg_handle* h, int l, T* u, const T* f, int steps, T* r, bool u_zero = false) {
   for (int s = 0; s < steps; ++s) {
     if (h->opts.smoother == DGMG_SMOOTHER_EA) {
-      int rc = k_sweep<T>(h, l, -1, u, f, r);
+      int rc = k_sweep<T>(h, l, -1, u, f, r, u_zero && s == 0);
       if (rc) return rc;
     } else {
       for (int d = 0; d < h->lv[l].dim; ++d) {
-        int rc = k_sweep<T>(h, l, d, u, f, r);
+        int rc = k_sweep<T>(h, l, d, u, f, r, u_zero && s == 0 && d == 0);
         if (rc) return rc;
       }
     }
@@ -655,7 +660,7 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
   for (int l = L; l >= 1; --l) {
     if (l < L) k_fill_v<T>(h, u[l], h->lv[l].n_dof);
     T* rl = (T*)h->buf[l].r;
-    int rc = k_smooth<T>(h, l, u[l], f[l], ns(l, 0), rl);
+    int rc = k_smooth<T>(h, l, u[l], f[l], ns(l, 0), rl, true);
     if (rc) return rc;
     rc = k_apply<T>(h, l, 1, u[l], f[l], rl, nullptr, nullptr);
     if (rc) return rc;
@@ -887,7 +892,7 @@ int autotune_t(dgmg_handle* h) {
       const int kind = nd < 0 ? 3 : nd;
       float best = 1e30f;
       int bw = 0;
-      for (int w : {1, 2, 4}) {
+      for (int w : {1, 2, 4, 8}) {
         if ((rc = k_fdm<T>(h, l, nd, r, w))) break;
         (void)hipEventRecord(e0, h->stream);
         for (int rep = 0; rep < 3; ++rep)
@@ -1181,7 +1186,7 @@ int dgmg_tune_get(const dgmg_handle* h, int level, int kind, int* waves, double*
 }
 
 int dgmg_tune_set(dgmg_handle* h, int level, int kind, int waves) {
-  if (!h || level < 1 || level >= (int)h->lv.size() || kind < 0 || kind >= NKIND || waves < 0 || waves > 4)
+  if (!h || level < 1 || level >= (int)h->lv.size() || kind < 0 || kind >= NKIND || waves < 0 || waves > 8)
     return DGMG_EINVAL;
   h->waves[level][kind] = waves;
   drop_graphs(h);
@@ -1567,7 +1572,7 @@ int dgmg_batch_autotune(dgmg_batch* b) {
         (void)hipEventCreate(&e1);
         float best = 1e30f;
         int bw = 0;
-        for (int w : {1, 2, 4}) {
+        for (int w : {1, 2, 4, 8}) {
           const bool f32 = mixed(h);
           auto launch = [&]() {
             return f32 ? k_fdm<float>(h, l, nd, (const float*)h->buf[l].r, w)

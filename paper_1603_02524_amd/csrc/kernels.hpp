@@ -18,6 +18,15 @@ constexpr int round64(int a) { return (a + 63) / 64 * 64; }
 
 constexpr int NUM_XCD = 8;  // MI355X: 8 accelerator complex dies, blocks dispatched round-robin
 
+// Patch-solve code shape: keep the 1D bases of tiles up to 16 long in registers
+// for the whole kernel, and the number of 16-line blocks a wave contracts at once.
+#ifndef DGMG_FDM_PRELOAD
+#define DGMG_FDM_PRELOAD 0
+#endif
+#ifndef DGMG_FDM_MBLK
+#define DGMG_FDM_MBLK 1
+#endif
+
 // Logical block index such that each XCD receives one contiguous range of
 // logical blocks (neighbouring elements then share that XCD's L2).  The grid
 // is launched with NUM_XCD * ceil(G / NUM_XCD) blocks; returns -1 for padding.
@@ -103,22 +112,22 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = apply_epb<NP, DIM>();
   constexpr int P = NP - 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sx = reinterpret_cast<T*>(smem_raw);
-  T* sy = sx + EPB * NE;
+  // only the accumulator lives in LDS; lines of x are read from global memory
+  // (each element's lines are read once per direction, then served by L1/L2)
+  T* sy = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[16];
+  __shared__ T sLs[NP * NP];  // stiffness matrix: uniform-address (broadcast) reads
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
   const int e0 = blk * EPB;
   const int ne = imin(EPB, L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int64_t g0 = (int64_t)e0 * NE;
-  for (int q = tid; q < ne * NE; q += nth) {
-    sx[q] = x[g0 + q];
-    sy[q] = T(0);
-  }
+  for (int q = tid; q < ne * NE; q += nth) sy[q] = T(0);
+  for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
   __syncthreads();
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
-  const T* __restrict__ Ls = L.Ls;
+  const T* __restrict__ Ls = sLs;
   const T* __restrict__ D0 = L.D;
   const T* __restrict__ DP = L.D + P * NP;
   const T* __restrict__ rho = L.rho;
@@ -142,36 +151,33 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       } else {
         ia = t % NP; ib = t / NP; base = t; stride = NP * NP;
       }
+      // neighbour lines first (unconditional loads at a valid address, masked
+      // below) so that their latency overlaps the LDS reads and the volume work
+      const int nl = dd.nbr[2 * m[d]], nr = dd.nbr[2 * m[d] + 1];
+      const T* wl = x + (int64_t)(e + (nl >= 0 ? nl - m[d] : 0) * estride) * NE + base;
+      const T* wr = x + (int64_t)(e + (nr >= 0 ? nr - m[d] : 0) * estride) * NE + base;
+      T wlv[NP], wrv[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        wlv[k] = wl[k * stride];
+        wrv[k] = wr[k * stride];
+      }
       T v[NP];
 #pragma unroll
-      for (int k = 0; k < NP; ++k) v[k] = sx[el * NE + base + k * stride];
+      for (int k = 0; k < NP; ++k) v[k] = x[g0 + el * NE + base + k * stride];
       const T* c = dd.ecoef + m[d] * ECOEF_N;
-      T d0 = 0, dP = 0;
+      T d0 = 0, dP = 0, dL = 0, dR = 0;
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
         d0 += D0[k] * v[k];
         dP += DP[k] * v[k];
+        dL += DP[k] * wlv[k];
+        dR += D0[k] * wrv[k];
       }
-      const int nl = dd.nbr[2 * m[d]], nr = dd.nbr[2 * m[d] + 1];
-      T uL = 0, dL = 0, uR = 0, dR = 0;
-      if (nl >= 0) {
-        const T* w = x + (int64_t)(e + (nl - m[d]) * estride) * NE + base;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const T wk = w[k * stride];
-          dL += DP[k] * wk;
-          if (k == P) uL = wk;
-        }
-      }
-      if (nr >= 0) {
-        const T* w = x + (int64_t)(e + (nr - m[d]) * estride) * NE + base;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const T wk = w[k * stride];
-          dR += D0[k] * wk;
-          if (k == 0) uR = wk;
-        }
-      }
+      const T ml = nl >= 0 ? T(1) : T(0), mr = nr >= 0 ? T(1) : T(0);
+      const T uL = ml * wlv[P], uR = mr * wrv[0];
+      dL *= ml;
+      dR *= mr;
       const T jl = v[0] - uL, jr = v[P] - uR;
       const T fl = c[E_CL] * d0 + c[E_CNL] * dL + c[E_BL] * jl;
       const T fr = -c[E_CR] * dP - c[E_CNR] * dR + c[E_BR] * jr;
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
         mo = L.dir[da].ecoef[m[da] * ECOEF_N + E_HALF_DX] * rho[ia] *
              L.dir[db].ecoef[m[db] * ECOEF_N + E_HALF_DX] * rho[ib];
       }
-#pragma unroll
+#pragma unroll 1  // one row of Ls live at a time (keeps registers for the line data)
       for (int i = 0; i < NP; ++i) {
         T s = 0;
 #pragma unroll
@@ -208,7 +214,7 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       y[g0 + q] = f[g0 + q] - val;
     } else {
       y[g0 + q] = val;
-      acc += (double)sx[q] * (double)val;
+      acc += (double)x[g0 + q] * (double)val;
     }
   }
   if (MODE == 2) {
@@ -222,7 +228,7 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
                  int* nblk_out, hipStream_t s) {
   constexpr int NE = ipow(NP, DIM), EPB = apply_epb<NP, DIM>(), TH = apply_threads<NP, DIM>();
   const int nblk = (L.n_elem + EPB - 1) / EPB;
-  const size_t shm = 2 * (size_t)EPB * NE * sizeof(T);
+  const size_t shm = (size_t)EPB * NE * sizeof(T);
   if (nblk_out) *nblk_out = nblk;
   dim3 grid(xcd_grid(nblk)), block(TH);
   if (mode == 0) {
@@ -299,55 +305,91 @@ __device__ __forceinline__ int fdm_line_base(int line) {
   return TD == 1 ? q * NAP * NL + a : q * NAP + a;
 }
 
+// B operand of a contraction (a row-major LEN x LEN matrix) in registers: lane
+// (li, lk) = (lane % 16, lane / 16) holds B[4 ks + lk][16 nb + li].
+template <class T, int LEN>
+struct BOp {
+  static constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16;
+  T b[NB][KS];
+  __device__ __forceinline__ void load(const T* __restrict__ Bm) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lk, j = nb * 16 + li;
+        b[nb][ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
+      }
+  }
+};
+
 // One contraction pass over tile dimension TD: every line v (length LEN) is
-// replaced by B^T v, i.e. out_j = sum_k B[k][j] v_k, with B row-major (LEN x LEN)
-// in global memory.  The lines form the M dimension in blocks of 16; each wave
-// owns whole blocks, reads them (A operand) and writes them back in place.
+// replaced by B^T v, i.e. out_j = sum_k B[k][j] v_k.  The lines form the M
+// dimension in blocks of 16; each wave owns whole blocks and works on
+// DGMG_FDM_MBLK of them at a time (independent accumulation chains), reading
+// them (A operand) completely before writing them back in place.
 template <class T, int NA, int NL, int DIM, int TD>
-__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm) {
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD == 0 ? NA : NL>& B) {
   constexpr int NAP = fdm_pitch<NA>();
   constexpr int LEN = TD == 0 ? NA : NL;
   constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
   constexpr int STRIDE = TD == 0 ? 1 : (TD == 1 ? NAP : NAP * NL);
-  constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16, MB = (LINES + 15) / 16;
+  constexpr int KS = BOp<T, LEN>::KS, NB = BOp<T, LEN>::NB, MB = (LINES + 15) / 16;
+  constexpr int MBLK = DGMG_FDM_MBLK;
   using M = Mfma<T>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  T b[NB][KS];
+  for (int mb0 = wave; mb0 < MB; mb0 += MBLK * nw) {
+    int base[MBLK];
+    bool lv[MBLK], act[MBLK];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + lk, j = nb * 16 + li;
-      b[nb][ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
+    for (int t = 0; t < MBLK; ++t) {
+      const int mb = mb0 + t * nw, line = mb * 16 + li;
+      act[t] = mb < MB;  // wave-uniform
+      lv[t] = act[t] && line < LINES;
+      base[t] = lv[t] ? fdm_line_base<NA, NL, TD>(line) : 0;
     }
-  for (int mb = wave; mb < MB; mb += nw) {
-    const int line = mb * 16 + li;
-    const bool lv = line < LINES;
-    const int base = lv ? fdm_line_base<NA, NL, TD>(line) : 0;
-    typename M::acc_t acc[NB];
+    typename M::acc_t acc[MBLK][NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename M::acc_t{0, 0, 0, 0};
+    for (int t = 0; t < MBLK; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[t][nb] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + lk;
-      const T a = (lv && k < LEN) ? tile[base + k * STRIDE] : T(0);
+      T a[MBLK];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, b[nb][ks], acc[nb]);
+      for (int t = 0; t < MBLK; ++t) a[t] = (lv[t] && k < LEN) ? tile[base[t] + k * STRIDE] : T(0);
+#pragma unroll
+      for (int t = 0; t < MBLK; ++t)
+        if (act[t])
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = M::op(a[t], B.b[nb][ks], acc[t][nb]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int oline = mb * 16 + M::row(lk, r);
-      if (oline < LINES) {
-        const int ob = fdm_line_base<NA, NL, TD>(oline);
+    for (int t = 0; t < MBLK; ++t) {
+      if (!act[t]) continue;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int j = nb * 16 + li;
-          if (j < LEN) tile[ob + j * STRIDE] = acc[nb][r];
+      for (int r = 0; r < 4; ++r) {
+        const int ol = (mb0 + t * nw) * 16 + M::row(lk, r);
+        if (ol < LINES) {
+          const int ob = fdm_line_base<NA, NL, TD>(ol);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int j = nb * 16 + li;
+            if (j < LEN) tile[ob + j * STRIDE] = acc[t][nb][r];
+          }
         }
       }
     }
   }
+}
+
+template <class T, int NA, int NL, int DIM, int TD>
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm) {
+  BOp<T, TD == 0 ? NA : NL> B;
+  B.load(Bm);
+  fdm_pass<T, NA, NL, DIM, TD>(tile, B);
 }
 
 // Tile geometry of one sweep kind, all compile-time: ND = normal direction of a
@@ -378,7 +420,7 @@ struct FdmShape {
 };
 
 template <class T, int DIM, int NA, int NL, int ND>
-__global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
+__global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
                                                   int npx, int npy, int npz) {
   using S = FdmShape<DIM, ND, NA, NL>;
   constexpr int TS = S::TS;
@@ -439,6 +481,21 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, const T* __rest
       bwd[t] = dd.ST_ec + (int64_t)p[d] * NL * NL;
     }
   }
+  // small bases (lengths <= 16: four values per lane and pass) are loaded into
+  // registers once, their latency hidden behind the gather
+  constexpr bool PRE = DGMG_FDM_PRELOAD && NA <= 16 && NL <= 16;
+  BOp<T, NA> F0, B0;
+  BOp<T, NL> F1, B1, F2, B2;
+  if constexpr (PRE) {
+    F0.load(fwd[0]);
+    F1.load(fwd[1]);
+    B0.load(bwd[0]);
+    B1.load(bwd[1]);
+    if constexpr (DIM == 3) {
+      F2.load(fwd[2]);
+      B2.load(bwd[2]);
+    }
+  }
   __syncthreads();
   // gather R_s r in grid-natural order (coalesced global reads); GU loads are
   // issued before their LDS stores; positions outside a Dirichlet domain read
@@ -462,12 +519,12 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, const T* __rest
       if (pos[u] >= 0) tile[pos[u]] = v[u];
   }
   __syncthreads();
-  fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, F0); else fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
   __syncthreads();
-  fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
   __syncthreads();
   if constexpr (DIM == 3) {
-    fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, F2); else fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2]);
     __syncthreads();
   }
   // diagonal scale by the reciprocal sum of 1D eigenvalues
@@ -481,12 +538,12 @@ __global__ void __launch_bounds__(256) fdm_kernel(LevelDev<T> L, const T* __rest
   }
   __syncthreads();
   if constexpr (DIM == 3) {
-    fdm_pass<T, NA, NL, DIM, 2>(tile, bwd[2]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, B2); else fdm_pass<T, NA, NL, DIM, 2>(tile, bwd[2]);
     __syncthreads();
   }
-  fdm_pass<T, NA, NL, DIM, 1>(tile, bwd[1]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, B1); else fdm_pass<T, NA, NL, DIM, 1>(tile, bwd[1]);
   __syncthreads();
-  fdm_pass<T, NA, NL, DIM, 0>(tile, bwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, B0); else fdm_pass<T, NA, NL, DIM, 0>(tile, bwd[0]);
   __syncthreads();
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
@@ -510,12 +567,12 @@ void fdm_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, i
                      npz);
 }
 
-// waves: wavefronts per block (1, 2 or 4; 0 = default), the shape the autotuner picks.
+// waves: wavefronts per block (1 .. 8; 0 = default), the shape the autotuner picks.
 template <class T, int DIM, int NA, int NL>
 int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
                  int waves, hipStream_t s) {
   constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
-  const int th = (waves >= 1 && waves <= 4) ? 64 * waves : fdm_threads<NA, NL, DIM>();
+  const int th = (waves >= 1 && waves <= 8) ? 64 * waves : fdm_threads<NA, NL, DIM>();
   if (nd < 0) {
     if constexpr (NA == NL) {
       fdm_launch_nd<T, DIM, NA, NL, -1>(L, r, out, npx, npy, npz, th, shm, s);
@@ -541,13 +598,14 @@ constexpr int combine_epb() {
   return imax(1, 256 / ipow(NP, DIM));
 }
 
-template <class T, int DIM, int NP>
+template <class T, int DIM, int NP, int MAXC>
 __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
                                                       const T* __restrict__ buf, T* __restrict__ u,
                                                       int npx, int npy, int npz, int nblk) {
   constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>();
   constexpr int P = NP - 1;
-  __shared__ int64_t cadr[EPB][3][NP][3];
+  constexpr int CZ = DIM == 3 ? MAXC : 1;
+  __shared__ int64_t cadr[EPB][3][NP][MAXC];
   __shared__ int ccnt[EPB][3][NP];
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
@@ -577,27 +635,41 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
       if (i >= NP - NO && (dd.periodic || md < N - 1)) { cp[c] = (md + 1) % N; co[c++] = i - NP + NO; }
     }
     ccnt[el][d][i] = c;
-    for (int k = 0; k < c; ++k) cadr[el][d][i][k] = cp[k] * pst[d] * TS + co[k] * ost[d];
+    for (int k = 0; k < MAXC; ++k) cadr[el][d][i][k] = k < c ? cp[k] * pst[d] * TS + co[k] * ost[d] : 0;
   }
   if (DIM == 2)
     for (int q = tid; q < ne; q += nth) {
       ccnt[q][2][0] = 1;
-      cadr[q][2][0][0] = 0;
+      for (int k = 0; k < MAXC; ++k) cadr[q][2][0][k] = 0;
     }
   __syncthreads();
+  // each node: all its (at most MAXC per direction) candidates are loaded before
+  // the sum, then added in a fixed order (z, y, x candidates)
   const int64_t g0 = (int64_t)e0 * NE;
   for (int q = tid; q < ne * NE; q += nth) {
     const int el = q / NE, loc = q - el * NE;
     const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
     const int nx = ccnt[el][0][i], ny = ccnt[el][1][j], nz = ccnt[el][2][k];
+    T v[CZ][MAXC][MAXC];
+#pragma unroll
+    for (int c = 0; c < CZ; ++c)
+#pragma unroll
+      for (int b = 0; b < MAXC; ++b)
+#pragma unroll
+        for (int a = 0; a < MAXC; ++a) {
+          // invalid candidates read buf[0] (valid) and are dropped from the sum
+          const bool ok = c < nz && b < ny && a < nx;
+          const int64_t ad = ok ? cadr[el][2][k][c] + cadr[el][1][j][b] + cadr[el][0][i][a] : 0;
+          v[c][b][a] = buf[ad];
+        }
     T s = 0;
-    for (int c = 0; c < nz; ++c) {
-      const int64_t az = cadr[el][2][k][c];
-      for (int b = 0; b < ny; ++b) {
-        const int64_t ayz = az + cadr[el][1][j][b];
-        for (int a = 0; a < nx; ++a) s += buf[ayz + cadr[el][0][i][a]];
-      }
-    }
+#pragma unroll
+    for (int c = 0; c < CZ; ++c)
+#pragma unroll
+      for (int b = 0; b < MAXC; ++b)
+#pragma unroll
+        for (int a = 0; a < MAXC; ++a)
+          s += T(c < nz && b < ny && a < nx ? 1 : 0) * v[c][b][a];  // s + 0 v = s: order unchanged
     u[g0 + q] += s;
   }
 }
@@ -607,8 +679,13 @@ int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf,
                      int npy, int npz, hipStream_t s) {
   constexpr int EPB = combine_epb<NP, DIM>();
   const int nblk = (L.n_elem + EPB - 1) / EPB;
-  hipLaunchKernelGGL((combine_kernel<T, DIM, NP>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
-                     NL, buf, u, npx, npy, npz, nblk);
+  // three covering element-centred patches in one direction only when 2 N_O > N_P
+  if (2 * L.NO > NP)
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
+                       NL, buf, u, npx, npy, npz, nblk);
+  else
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 2>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
+                       NL, buf, u, npx, npy, npz, nblk);
   return 0;
 }
 

@@ -86,14 +86,15 @@ def params_to_outputs(theta, omega):
 
 # ---------------------------------------------------------------------- data
 def training_problems(seed=11, count=24):
-    """3D Dirichlet FA problems, P in {4, 8, 16} on 8^3 / 8^3 / 6^3 elements, aspect ratios 1 .. 32."""
+    """3D Dirichlet FA problems, P in {4, 8, 16, 32} on 8^3 / 8^3 / 6^3 / 4^3 elements,
+    aspect ratios 1 .. 32 (per-direction sizes 2^U(0, a), a in {0, 2, 3.5, 5})."""
     import synth
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
-        P = (4, 8, 16)[k % 3]
-        n = 8 if P < 16 else 6
-        max_log2 = (0.0, 2.0, 3.5, 5.0)[(k // 3) % 4]
+        P = (4, 8, 16, 32)[k % 4]
+        n = {4: 8, 8: 8, 16: 6, 32: 4}[P]
+        max_log2 = (0.0, 2.0, 3.5, 5.0)[(k // 4) % 4]
         dx = tuple(synth.random_spacing(rng, n, max_log2, 1.0) for _ in range(3))
         g = synth.Grid(3, dx, (False, False, False))
         m = synth.Method(P=P, smoother="FA", overlap="level")
@@ -172,7 +173,7 @@ def train(X, Y, steps=3000, lr=3e-3, seed=0, log=None):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default=DEFAULT_PARAMS)
-    ap.add_argument("--problems", type=int, default=24)
+    ap.add_argument("--problems", type=int, default=32)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--report", default=None, help="JSON summary path")
     a = ap.parse_args(argv)

@@ -59,16 +59,16 @@ def test_autotune_is_bitwise_neutral():
     S.solve(f, x1)
     tune = S.autotune()
     assert len(tune) == 3 * (S.num_levels - 1)   # FA: three sweep kinds per smoothing level
-    assert all(w in (1, 2, 4) and ms > 0 for (w, ms) in tune.values())
+    assert all(w in (1, 2, 4, 8) and ms > 0 for (w, ms) in tune.values())
     x2 = _dev(np.zeros(n))
     S.solve(f, x2)
     assert torch.equal(x1, x2)
-    for (l, kind), (w, _) in tune.items():         # every forced shape gives the same result
-        for w2 in (1, 2, 4):
+    for w2 in (1, 2, 4, 8):                          # every forced shape gives the same result
+        for (l, kind) in tune:
             S.set_tuning(l, kind, w2)
-    x3 = _dev(np.zeros(n))
-    S.solve(f, x3)
-    assert torch.equal(x1, x3)
+        x3 = _dev(np.zeros(n))
+        S.solve(f, x3)
+        assert torch.equal(x1, x3), w2
     S.close()
 
 
