@@ -70,7 +70,85 @@ def _workload(name):
         return synth.c2_poisson3d_p8(n=8)
     if name == "c3":
         return synth.c3_ldg3d_stretched()
+    if name == "c5":
+        return synth.c5_poisson3d_p32()
     raise SystemExit(f"unknown workload {name}")
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def _top_kernel(S, m):
+    """Name, element type and peak of the top-level patch-solve kernel."""
+    L = S.num_levels - 1
+    P, n_o, _ = S.level_info(L)
+    nl = P + 1 + 2 * n_o
+    na = 2 * P if m.smoother == "FA" else nl
+    f64 = m.precision == "fp64"
+    t = "double" if f64 else "float"
+    big = S.grid.dim == 3 and P == 32
+    name = (f"fdm_big_{{a,b,c}}<{t},{na},{nl}>" if big else f"fdm_kernel<{t},3,{na},{nl}>") + \
+        f" ({'face' if m.smoother == 'FA' else 'element'}-centred patch solve, P={P}, N_O={n_o})"
+    return name, (FP64_VALU_PEAK_TFLOPS if f64 else FP32_MFMA_PEAK_TFLOPS)
+
+
+def _run_batch(args):
+    """Many grids (3D, 4^3..16^3 elements, P in {4, 6, 8, 12, 16}) solved together."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1603_02524_amd import dgmg
+    ws = synth.c4_batched()
+    _log(f"setup {len(ws)} grids")
+    B = dgmg.BatchSolver([(w.grid, w.method) for w in ws], max_iter=200)
+    n = B.n_dof
+    rhs = torch.tensor(np.concatenate([synth.rhs_uniform(w.seed, w.grid.n_dof(w.method.P)) for w in ws]),
+                       device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    if not args.no_autotune:
+        _log("autotuning")
+        B.autotune()
+    for _ in range(args.warmup):
+        x.zero_()
+        B.solve(rhs, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        st = B.solve(rhs, x)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    its = [s["iterations"] for s in st]
+    out = {"metric": METRIC, "value": n / sec, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
+           "config": {"workload": f"batched_{len(ws)}_grids_3d_mixed", "grids": len(ws), "n_dof": n,
+                      "iterations_min_max": [min(its), max(its)], "converged": all(s["converged"] for s in st),
+                      "graphs": True}}
+    if not args.no_mixed:
+        # the same grids one after another with the plain FP64 solver (one handle each)
+        _log("timing the same grids one by one in FP64")
+        tot = 0.0
+        for w, (a, b) in zip(ws, zip(B.offsets[:-1], B.offsets[1:])):
+            m64 = synth.with_method(w, precision="fp64").method
+            S = dgmg.Solver(w.grid, m64, max_iter=200)
+            if not args.no_autotune:
+                S.autotune()
+            xs = torch.zeros(b - a, dtype=torch.float64, device="cuda")
+            r = rhs[a:b].contiguous()
+            S.solve(r, xs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(max(1, args.steps // 2)):
+                xs.zero_()
+                S.solve(r, xs)
+            torch.cuda.synchronize()
+            tot += (time.perf_counter() - t0) / max(1, args.steps // 2)
+            S.close()
+        out["fp64_one_by_one"] = {"value": n / tot, "unit": "DoF/s", "ms_per_step": tot * 1e3,
+                                  "batched_time_per_dof_vs_fp64": sec / tot}
+    B.close()
+    print(json.dumps(out), flush=True)
 
 
 def _log(msg):
@@ -128,10 +206,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2small", "c3", "c4", "c5"],
+                    help="c2 (default): 16^3 P=8 FP64; c3: 32^3 stretched LDG mixed; c4: 64 batched grids; "
+                         "c5: 8^3 P=32 mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="also time the solver with the shipped learned face weights")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB MiB (PMC calibration) and exit")
@@ -143,6 +225,10 @@ def main():
 
     if args.copy_calibration:
         _copy_calibration(args.copy_calibration)
+        return
+
+    if args.workload == "c4":
+        _run_batch(args)
         return
 
     import numpy as np
@@ -165,9 +251,9 @@ def main():
         tuning = S.autotune()
     else:
         tuning = {}
-    _log("timing FP64 solves")
+    _log(f"timing {m.precision} solves")
     sec, st, kt = _time_solves(S, rhs, x, w.tol, args.warmup, args.steps, timing=True)
-    _log(f"FP64: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
+    _log(f"{m.precision}: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
     # true residual of the final iterate (outside the timed region)
     r = S.residual(S.num_levels - 1, rhs, x)
     true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(rhs))
@@ -182,17 +268,19 @@ def main():
     k_bytes = kt["bytes"] / max(kt["launches"], 1)
     achieved = k_flops / (k_ms * 1e-3) / 1e12
     traffic = None
-    if TRAFFIC["bytes_per_launch"] and TRAFFIC["kernel_src_sha256"] == _kernel_src_hash():
+    if (args.workload == "c2" and TRAFFIC["bytes_per_launch"]
+            and TRAFFIC["kernel_src_sha256"] == _kernel_src_hash()):
         traffic = TRAFFIC["bytes_per_launch"]
-    roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": "fdm_kernel<double,3,16,13> (face-centred patch solve, P=8, N_O=2)",
+    kname, peak = _top_kernel(S, m)
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "kernel": kname,
             "avg_ms": k_ms, "launches": kt["launches"], "flops_per_launch": k_flops,
             "alg_bytes_per_launch": k_bytes, "alg_GBps": k_bytes / (k_ms * 1e-3) / 1e9}
 
     out = {"metric": METRIC, "value": n / sec, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if m.precision == "fp64" else "f64/f32",
+           "data": "synthetic",
            "config": {"workload": w.name, "elements": list(g.n), "P": m.P, "n_dof": n,
                       "flux": m.flux, "smoother": f"{m.smoother}_l", "vcycle": "V(1,1)",
                       "precision": m.precision, "tol": w.tol, "seed": w.seed,
@@ -202,19 +290,39 @@ def main():
            "roofline": roof}
 
     if not args.no_mixed:
-        _log("timing mixed-precision solves")
-        wm = synth.with_method(w, precision="mixed")
+        # the other precision on the same workload: mixed vs FP64 time per DoF
+        other = "mixed" if m.precision == "fp64" else "fp64"
+        _log(f"timing {other} solves")
+        wm = synth.with_method(w, precision=other)
         Sm = dgmg.Solver(wm.grid, wm.method, max_iter=200)
         if not args.no_autotune:
             Sm.autotune()
         xm = torch.zeros(n, dtype=torch.float64, device="cuda")
         secm, stm, _ = _time_solves(Sm, rhs, xm, w.tol, args.warmup, args.steps, timing=False)
         rm = Sm.residual(Sm.num_levels - 1, rhs, xm)
-        out["mixed"] = {"value": n / secm, "unit": "DoF/s", "ms_per_step": secm * 1e3,
-                        "iterations": stm["iterations"],
-                        "true_rel_residual": float(torch.linalg.norm(rm) / torch.linalg.norm(rhs)),
-                        "time_per_dof_vs_fp64": secm / sec}
+        t_mixed, t_fp64 = (secm, sec) if other == "mixed" else (sec, secm)
+        out[other] = {"value": n / secm, "unit": "DoF/s", "ms_per_step": secm * 1e3,
+                      "iterations": stm["iterations"],
+                      "true_rel_residual": float(torch.linalg.norm(rm) / torch.linalg.norm(rhs)),
+                      "mixed_time_per_dof_vs_fp64": t_mixed / t_fp64}
         Sm.close()
+
+    if args.learned and m.smoother == "FA":
+        # learned face weights (shipped network, probe fallback) on the main solver
+        from paper_1603_02524_amd import learn
+        if os.path.exists(learn.DEFAULT_PARAMS):
+            _log("timing solves with learned face weights")
+            params = torch.tensor(learn.load_params(), device="cuda")
+            kept, rl, rf = S.apply_mlp(params, probe_iters=4)
+            xl = torch.zeros(n, dtype=torch.float64, device="cuda")
+            secl, stl, _ = _time_solves(S, rhs, xl, w.tol, args.warmup, args.steps, timing=False)
+            rl_true = S.residual(S.num_levels - 1, rhs, xl)
+            out["learned"] = {"kept": kept, "probe_ratio_learned": rl, "probe_ratio_fixed": rf,
+                              "value": n / secl, "unit": "DoF/s", "ms_per_step": secl * 1e3,
+                              "iterations": stl["iterations"],
+                              "true_rel_residual": float(torch.linalg.norm(rl_true) / torch.linalg.norm(rhs)),
+                              "time_per_dof_vs_fixed": secl / sec}
+            S.set_face_params(None)
 
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle on a bounded sample")

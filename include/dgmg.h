@@ -129,7 +129,8 @@ int dgmg_opts_default(dgmg_opts* o);
  * touched.  On success *out owns a new handle (free with dgmg_destroy).
  * Errors: DGMG_EINVAL for dim not in {2,3}, P out of range, n_elem < 1,
  * dx <= 0 or not finite, mu_star <= 0, |beta| > 1, periodic with n_elem < 3,
- * bad enum values; DGMG_EUNSUPPORTED for (P, N_O) pairs without kernels. */
+ * bad enum values, more than 2^31 - 1 unknowns on the top level;
+ * DGMG_EUNSUPPORTED for (P, N_O) pairs without kernels. */
 int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out);
 
 /* Bytes of device workspace the handle needs (tables, level vectors, patch

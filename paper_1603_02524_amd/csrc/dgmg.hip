@@ -864,7 +864,8 @@ int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   }
   int64_t ne = 1;
   for (int d = 0; d < g->dim; ++d) ne *= g->n_elem[d];
-  if (ne * (int64_t)std::pow(o->P + 1, g->dim) > (int64_t)INT32_MAX * 4) return fail(nullptr, DGMG_EINVAL, "problem too large");
+  if (ne * (int64_t)std::pow(o->P + 1, g->dim) > (int64_t)INT32_MAX)
+    return fail(nullptr, DGMG_EINVAL, "problem too large (at most 2^31 - 1 unknowns)");
   sp.P = o->P;
   sp.flux = o->flux;
   for (int d = 0; d < 3; ++d) sp.beta[d] = o->beta[d];

@@ -328,8 +328,16 @@ struct BOp {
 // dimension in blocks of 16; each wave owns whole blocks and works on
 // DGMG_FDM_MBLK of them at a time (independent accumulation chains), reading
 // them (A operand) completely before writing them back in place.
-template <class T, int NA, int NL, int DIM, int TD>
-__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD == 0 ? NA : NL>& B) {
+struct NoPost {
+  template <class T>
+  __device__ __forceinline__ T operator()(int, int, T v) const { return v; }
+};
+
+// post(line, j, value) maps each result before it is stored (e.g. the
+// eigenvalue scaling fused into the last forward pass).
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD == 0 ? NA : NL>& B,
+                                         Post post = Post()) {
   constexpr int NAP = fdm_pitch<NA>();
   constexpr int LEN = TD == 0 ? NA : NL;
   constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
@@ -377,7 +385,7 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int j = nb * 16 + li;
-            if (j < LEN) tile[ob + j * STRIDE] = acc[t][nb][r];
+            if (j < LEN) tile[ob + j * STRIDE] = post(ol, j, acc[t][nb][r]);
           }
         }
       }
@@ -385,11 +393,11 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
   }
 }
 
-template <class T, int NA, int NL, int DIM, int TD>
-__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm) {
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm, Post post = Post()) {
   BOp<T, TD == 0 ? NA : NL> B;
   B.load(Bm);
-  fdm_pass<T, NA, NL, DIM, TD>(tile, B);
+  fdm_pass<T, NA, NL, DIM, TD, Post>(tile, B, post);
 }
 
 // Tile geometry of one sweep kind, all compile-time: ND = normal direction of a
@@ -428,7 +436,7 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   constexpr int GU = 4;  // elements gathered per thread before their LDS stores (loads in flight)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
-  __shared__ int64_t goff[3][NMAX];
+  __shared__ int goff[3][NMAX];  // offsets into the level vector (< 2^31 unknowns), -1 outside
   __shared__ T wv[3][NMAX];
   __shared__ T lv[3][NMAX];
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
@@ -454,11 +462,11 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     const T* lam = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
     for (int o = tid; o < len; o += nth) {
       int g = start + o;
-      int64_t off = -1;
+      int off = -1;
       if (dd.periodic) g = ((g % G) + G) % G;
       if (g >= 0 && g < G) {
         const int mm = g / NP, ii = g - mm * NP;
-        off = mm * est[d] + ii * nst[d];
+        off = (int)(mm * est[d] + ii * nst[d]);
       }
       goff[d][o] = off;
       wv[d][o] = w[o];
@@ -508,8 +516,8 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
       const int q = q0 + u * nth;
       int o0, o1, o2;
       S::split(q < TS ? q : 0, o0, o1, o2);
-      const int64_t g0 = goff[0][o0], g1 = goff[1][o1], g2 = DIM == 3 ? goff[2][o2] : 0;
-      const bool ok = q < TS && g0 >= 0 && g1 >= 0 && g2 >= 0;
+      const int g0 = goff[0][o0], g1 = goff[1][o1], g2 = DIM == 3 ? goff[2][o2] : 0;
+      const bool ok = q < TS && (g0 | g1 | g2) >= 0;
       v[u] = r[ok ? g0 + g1 + g2 : 0];
       v[u] = ok ? v[u] : T(0);
       pos[u] = q < TS ? S::tpos(o0, o1, o2) : -1;
@@ -519,22 +527,24 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
       if (pos[u] >= 0) tile[pos[u]] = v[u];
   }
   __syncthreads();
+  // the last forward pass divides each result by the sum of the 1D eigenvalues
+  // of its tile position: line = a + NA l1 (3D; a in 2D), j = l2 (3D; l1 in 2D)
+  const auto scale = [&](int line, int j, T v) -> T {
+    const int a = line % NA;
+    T den = lv[S::gd(0)][a] + lv[S::gd(1)][DIM == 3 ? line / NA : j];
+    if (DIM == 3) den += lv[S::gd(2)][j];
+    return v / den;
+  };
   if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, F0); else fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
   __syncthreads();
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
-  __syncthreads();
   if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, F2); else fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
     __syncthreads();
-  }
-  // diagonal scale by the reciprocal sum of 1D eigenvalues
-  for (int q = tid; q < TS; q += nth) {
-    const int a = q % NA, rest = q / NA;
-    const int l1 = DIM == 3 ? rest % NL : rest, l2 = DIM == 3 ? rest / NL : 0;
-    T den = lv[S::gd(0)][a] + lv[S::gd(1)][l1];
-    if (DIM == 3) den += lv[S::gd(2)][l2];
-    const int idx = (l2 * NL + l1) * S::NAP + a;
-    tile[idx] = tile[idx] / den;
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, F2, scale);
+    else fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2], scale);
+  } else {
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1, scale);
+    else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1], scale);
   }
   __syncthreads();
   if constexpr (DIM == 3) {
