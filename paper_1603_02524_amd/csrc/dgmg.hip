@@ -350,6 +350,27 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
         for (int j = 0; j < n; ++j) t[b * n * n + (size_t)j * n + i] = S[b * n * n + (size_t)i * n + j];
     return t;
   };
+  // gather offsets of every patch position into the level vector (element-major)
+  auto offsets = [&](int dir, int npatch, int len, bool fc) {
+    const Dir1D& s = h.dir[dir];
+    const int NP = h.NP, G = s.N * NP;
+    int64_t NE = 1;
+    for (int e = 0; e < h.dim; ++e) NE *= NP;
+    int64_t est = NE;
+    for (int e = 0; e < dir; ++e) est *= h.dir[e].N;
+    int64_t nst = 1;
+    for (int e = 0; e < dir; ++e) nst *= NP;
+    std::vector<int> t((size_t)npatch * len);
+    for (int q = 0; q < npatch; ++q)
+      for (int o = 0; o < len; ++o) {
+        int g = (fc ? (q - 1) * NP + 1 : q * NP - h.NO) + o;
+        if (s.periodic) g = ((g % G) + G) % G;
+        int off = -1;
+        if (g >= 0 && g < G) off = (int)((g / NP) * est + (g % NP) * nst);
+        t[(size_t)q * len + o] = off;
+      }
+    return t;
+  };
   d.dim = h.dim;
   d.P = h.P;
   d.NP = h.NP;
@@ -382,6 +403,8 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
       dd.ST_fc = put(transp(s.S_fc, s.n_fc));
       dd.lam_fc = put(s.lam_fc);
       dd.w_fc = put(s.w_fc);
+      dd.goff_ec = put_int(offsets(k, s.N, s.n_ec, false));
+      dd.goff_fc = put_int(offsets(k, s.nf, s.n_fc, true));
     }
   }
 }

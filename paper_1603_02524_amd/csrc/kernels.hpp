@@ -54,6 +54,10 @@ struct DirDev {
   const T* ST_fc = nullptr;
   const T* lam_fc = nullptr;
   const T* w_fc = nullptr;
+  // offsets into the level vector of every patch position (-1 outside a
+  // Dirichlet domain): N * n_ec and nf * n_fc
+  const int* goff_ec = nullptr;
+  const int* goff_fc = nullptr;
 };
 
 template <class T>
@@ -305,8 +309,9 @@ __device__ __forceinline__ int fdm_line_base(int line) {
   return TD == 1 ? q * NAP * NL + a : q * NAP + a;
 }
 
-// B operand of a contraction (a row-major LEN x LEN matrix) in registers: lane
-// (li, lk) = (lane % 16, lane / 16) holds B[4 ks + lk][16 nb + li].
+// The 1D matrix of a contraction (row-major LEN x LEN) in registers: lane
+// (li, lk) = (lane % 16, lane / 16) holds B[4 ks + lk][16 nb + li], i.e. the
+// A operand (B^T)[16 nb + li][4 ks + lk] of the transposed product.
 template <class T, int LEN>
 struct BOp {
   static constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16;
@@ -338,6 +343,9 @@ struct NoPost {
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
 __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD == 0 ? NA : NL>& B,
                                          Post post = Post()) {
+  // Product D = B^T V^T: the A operand is B^T (held as B.b), the B operand the
+  // lines; lane (li, lk) then owns output column li = its own line, rows
+  // j = 16 nb + row(lk, r), so results go back along the line it loaded.
   constexpr int NAP = fdm_pitch<NA>();
   constexpr int LEN = TD == 0 ? NA : NL;
   constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
@@ -372,23 +380,19 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
       for (int t = 0; t < MBLK; ++t)
         if (act[t])
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = M::op(a[t], B.b[nb][ks], acc[t][nb]);
+          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = M::op(B.b[nb][ks], a[t], acc[t][nb]);
     }
 #pragma unroll
     for (int t = 0; t < MBLK; ++t) {
-      if (!act[t]) continue;
+      if (!lv[t]) continue;
+      const int line = (mb0 + t * nw) * 16 + li;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ol = (mb0 + t * nw) * 16 + M::row(lk, r);
-        if (ol < LINES) {
-          const int ob = fdm_line_base<NA, NL, TD>(ol);
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const int j = nb * 16 + li;
-            if (j < LEN) tile[ob + j * STRIDE] = post(ol, j, acc[t][nb][r]);
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int j = nb * 16 + M::row(lk, r);
+          if (j < LEN) tile[base[t] + j * STRIDE] = post(line, j, acc[t][nb][r]);
         }
-      }
     }
   }
 }
@@ -443,32 +447,20 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   const int pid = xcd_block(npatch);
   if (pid < 0 || inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int NP = L.NP, NE = DIM == 3 ? NP * NP * NP : NP * NP;
   int p[3];
   p[0] = pid % npx;
   p[1] = (pid / npx) % npy;
   p[2] = DIM == 3 ? pid / (npx * npy) : 0;
-  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
-  const int64_t est[3] = {(int64_t)NE, (int64_t)N1 * NE, (int64_t)N1 * N2 * NE};
-  const int nst[3] = {1, NP, NP * NP};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const DirDev<T>& dd = L.dir[d];
     const bool fc = d == ND;
     const int len = fc ? NA : NL;
-    const int start = fc ? (p[d] - 1) * NP + 1 : p[d] * NP - L.NO;
-    const int G = dd.N * NP;
+    const int* go = fc ? dd.goff_fc + p[d] * NA : dd.goff_ec + p[d] * NL;
     const T* w = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
     const T* lam = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
     for (int o = tid; o < len; o += nth) {
-      int g = start + o;
-      int off = -1;
-      if (dd.periodic) g = ((g % G) + G) % G;
-      if (g >= 0 && g < G) {
-        const int mm = g / NP, ii = g - mm * NP;
-        off = (int)(mm * est[d] + ii * nst[d]);
-      }
-      goff[d][o] = off;
+      goff[d][o] = go[o];
       wv[d][o] = w[o];
       lv[d][o] = lam[o];
     }
