@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the DG p-multigrid MGCG solver on one MI355X.
 
-Workload (default): 3D Poisson on [0,1]^3, 16^3 uniform elements, SIPG with
-P = 8 (2,985,984 unknowns), homogeneous Dirichlet, right-hand side i.i.d.
-U[-1,1] (seed 2), face-centred additive Schwarz with level overlap, V(1,1),
-MGCG to a 1e-10 relative residual, FP64 throughout.  One step = one complete
-solve from x = 0 (every stage of the path: operator applies, patch solves,
-overlap summation, transfers, coarse solve, PCG updates).
+Workload (default, --workload c2): 3D Poisson on [0,1]^3, 16^3 uniform
+elements, SIPG with P = 8 (2,985,984 unknowns), homogeneous Dirichlet,
+right-hand side i.i.d. U[-1,1] (seed 2), face-centred additive Schwarz with
+level overlap, V(1,1), MGCG to a 1e-10 relative residual, FP64 throughout.
+One step = one complete solve from x = 0 (every stage of the path: operator
+applies, patch solves, overlap summation, transfers, coarse solve, PCG
+updates).  The other precision (FP32 V-cycle inside FP64 PCG) is timed on the
+same workload for the mixed-vs-FP64 ratio.
+
+Other workloads: c3 (32^3 LDG, z stretched to aspect ratio 32, mixed), c5
+(8^3 at P = 32 with random per-direction sizes, mixed; --learned adds the
+shipped face-weight network with its probe fallback), c4 (64 independent
+grids of 4^3..16^3 elements at P in {4,6,8,12,16} solved together in one
+batched, graph-replayed MGCG, against the same grids solved one by one in
+FP64).
 
 Prints one JSON line: DoF/s (unknowns / solve time), the live roofline of the
-dominant kernel (top-level patch solve, HIP events on the solver's stream) and
-the CPU oracle timed on a bounded sample of the same workload.
+dominant kernel (top-level patch solve, HIP events on the solver's stream),
+its HBM traffic when measured for the current kernel sources, and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 

@@ -462,9 +462,11 @@ void layout(dgmg_handle* h, char* base, Upload* up) {
     }
   }
   pmax = std::max(pmax, (size_t)l0.n_dof);
-  for (int l = 1; l < nl; ++l)  // scratch of the two-kernel transfers of large 3D elements
-    if (h->lv[l].dim == 3 && h->lv[l].NP == BIG_NP)
+  for (int l = 1; l < nl; ++l)  // scratch of the transfers and the apply of large 3D elements
+    if (h->lv[l].dim == 3 && h->lv[l].NP == BIG_NP) {
       pmax = std::max(pmax, (size_t)transfer_big_scratch((int)h->lv[l].n_elem, h->lv[l].NP, h->lv[l].NPc));
+      pmax = std::max(pmax, (size_t)apply_big_scratch((int)h->lv[l].n_elem, h->lv[l].NP));
+    }
   h->patch_elems = pmax;
   h->patch = cv.take(pmax * sizeof(double));
   const size_t n0 = l0.n_dof;
@@ -477,7 +479,11 @@ void layout(dgmg_handle* h, char* base, Upload* up) {
   h->pp = (double*)cv.take(nt * 8);
   h->pq = (double*)cv.take(nt * 8);
   h->pz = (double*)cv.take(nt * 8);
-  const size_t np1 = std::max<size_t>(RED_BLOCKS, h->lv.back().n_elem + 8);
+  // partial sums of the MODE-2 apply: one per block (several per element on large 3D elements)
+  const LevelHost& top = h->lv.back();
+  const size_t per_elem =
+      (top.dim == 3 && top.NP == BIG_NP) ? (size_t)apply_big_blocks_per_elem<double, BIG_NP>() : 1;  // FP64: most blocks
+  const size_t np1 = std::max<size_t>(RED_BLOCKS, top.n_elem * per_elem + 8);
   h->part = (double*)cv.take(np1 * 8);
   h->part2 = (double*)cv.take(RED_BLOCKS * 8);
   h->scal = (double*)cv.take(64 * 8);
@@ -499,8 +505,9 @@ const LevelDev<float>& LD<float>(dgmg_handle* h, int l) { return h->Lf[l]; }
 template <class T>
 int k_apply(dgmg_handle* h, int l, int mode, const T* x, const T* f, T* y, double* part, int* nb) {
   const LevelDev<T>& L = LD<T>(h, l);
-  int rc = L.dim == 3 ? Kern<T, 3>::apply(L, mode, x, f, y, part, nb, h->stream)
-                      : Kern<T, 2>::apply(L, mode, x, f, y, part, nb, h->stream);
+  T* scratch = (T*)h->patch;  // idle outside the patch solves of a sweep
+  int rc = L.dim == 3 ? Kern<T, 3>::apply(L, mode, x, f, y, scratch, part, nb, h->stream)
+                      : Kern<T, 2>::apply(L, mode, x, f, y, scratch, part, nb, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no operator kernel for this order");
   return check_hip(h, "apply");
 }

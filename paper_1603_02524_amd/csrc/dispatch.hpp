@@ -23,13 +23,13 @@ constexpr size_t LDS_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
   X(32, 17) X(32, 21) X(32, 23) X(33, 33) X(35, 35) X(43, 43) X(64, 33) X(64, 35) X(64, 43)
 
 template <class T, int DIM>
-int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
+int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
                         int* nblk, hipStream_t s) {
   switch (L.NP) {
 #define DGMG_CASE(NP)                                                              \
   case NP:                                                                         \
     if constexpr (DIM == 3 && NP == BIG_NP)                                        \
-      return apply_big_launch<T, NP>(L, mode, x, f, y, part, nblk, s);             \
+      return apply_big_launch<T, NP>(L, mode, x, f, y, scratch, part, nblk, s);    \
     else                                                                           \
       return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
     DGMG_NP_LIST(DGMG_CASE)
@@ -52,7 +52,7 @@ int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, 
                       int npy, int npz, int waves, hipStream_t s) {
 #define DGMG_CASE(A, B)                                                                   \
   if (NA == A && NL == B) {                                                               \
-    if constexpr (DIM == 3 && fdm_shmem<T, A, B, DIM>() + 4096 > LDS_BYTES)               \
+    if constexpr (DIM == 3 && fdm_lds_total<T, A, B, DIM>() > LDS_BYTES)                  \
       return fdm_big_launch<T, A, B>(L, nd, r, out, npx, npy, npz, s);                    \
     else                                                                                  \
       return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, s);          \

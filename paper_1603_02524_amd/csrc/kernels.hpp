@@ -277,6 +277,16 @@ constexpr size_t fdm_shmem() {
   return (size_t)fdm_tile_padded<NA, NL, DIM>() * sizeof(T);
 }
 
+// Whole LDS of one patch-solve block: the tile plus the per-direction and
+// per-row tables (largest over the sweep kinds) and some slack.
+template <class T, int NA, int NL, int DIM>
+constexpr size_t fdm_lds_total() {
+  constexpr int NMAX = imax(NA, NL);
+  constexpr int NROW = DIM == 3 ? imax(NL * NL, NA * NL) : imax(NL, NA);
+  return fdm_shmem<T, NA, NL, DIM>() + 3 * NMAX * (sizeof(int) + 2 * sizeof(T)) +
+         NROW * (2 * sizeof(int) + sizeof(T)) + 512;
+}
+
 // 16x16x4 matrix-core contraction (v_mfma_{f64,f32}_16x16x4): A[i][k] comes from lane
 // i + 16k and B[k][j] from lane j + 16k.  Result register r of lane l holds
 // D[row(l / 16, r)][l % 16] with row = l/16 + 4r for f64 and 4 (l/16) + r for f32
@@ -414,7 +424,10 @@ struct FdmShape {
   static constexpr int L1 = ND == 1 ? NA : NL;
   static constexpr int L2 = DIM == 3 ? (ND == 2 ? NA : NL) : 1;
   static constexpr int TS = L0 * L1 * L2;
+  static constexpr int NROW = L1 * L2;  // rows of the grid-natural order (fixed o1, o2)
   static constexpr int NAP = fdm_pitch<NA>();
+  // tile stride of direction 0 (the normal / fastest tile dimension unless ND > 0)
+  static constexpr int C0 = ND <= 0 ? 1 : NAP;
   // grid direction of tile dimension t (t = 0: the normal / fastest one)
   static constexpr int gd(int t) {
     return ND <= 0 ? t : (t == 0 ? ND : (t <= ND ? t - 1 : t));
@@ -443,6 +456,8 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   __shared__ int goff[3][NMAX];  // offsets into the level vector (< 2^31 unknowns), -1 outside
   __shared__ T wv[3][NMAX];
   __shared__ T lv[3][NMAX];
+  __shared__ int rowoff[S::NROW], rowpos[S::NROW];
+  __shared__ T roww[S::NROW];
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   const int pid = xcd_block(npatch);
   if (pid < 0 || inactive(L.active)) return;
@@ -451,19 +466,30 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   p[0] = pid % npx;
   p[1] = (pid / npx) % npy;
   p[2] = DIM == 3 ? pid / (npx * npy) : 0;
+  const int* go[3] = {nullptr, nullptr, nullptr};
+  const T* wg[3] = {nullptr, nullptr, nullptr};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const DirDev<T>& dd = L.dir[d];
     const bool fc = d == ND;
     const int len = fc ? NA : NL;
-    const int* go = fc ? dd.goff_fc + p[d] * NA : dd.goff_ec + p[d] * NL;
-    const T* w = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
+    go[d] = fc ? dd.goff_fc + p[d] * NA : dd.goff_ec + p[d] * NL;
+    wg[d] = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
     const T* lam = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
     for (int o = tid; o < len; o += nth) {
-      goff[d][o] = go[o];
-      wv[d][o] = w[o];
+      goff[d][o] = go[d][o];
+      wv[d][o] = wg[d][o];
       lv[d][o] = lam[o];
     }
+  }
+  // per row (o1, o2) of the grid-natural order: its offset in the level vector
+  // (-1 outside a Dirichlet domain), its tile position and its weight w1 w2
+  for (int rw = tid; rw < S::NROW; rw += nth) {
+    const int o1 = DIM == 3 ? rw % S::L1 : rw, o2 = DIM == 3 ? rw / S::L1 : 0;
+    const int g1 = go[1][o1], g2 = DIM == 3 ? go[2][o2] : 0;
+    rowoff[rw] = (g1 | g2) < 0 ? -1 : g1 + g2;
+    rowpos[rw] = S::tpos(0, o1, o2);
+    roww[rw] = DIM == 3 ? wg[1][o1] * wg[2][o2] : wg[1][o1];
   }
   // 1D matrices of each tile dimension: forward t_j = sum_k S_kj r_k uses S,
   // backward u_k = sum_j S_kj t_j uses S^T (both row-major)
@@ -506,13 +532,13 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int q = q0 + u * nth;
-      int o0, o1, o2;
-      S::split(q < TS ? q : 0, o0, o1, o2);
-      const int g0 = goff[0][o0], g1 = goff[1][o1], g2 = DIM == 3 ? goff[2][o2] : 0;
-      const bool ok = q < TS && (g0 | g1 | g2) >= 0;
-      v[u] = r[ok ? g0 + g1 + g2 : 0];
+      const int qq = q < TS ? q : 0;
+      const int o0 = qq % S::L0, rw = qq / S::L0;
+      const int g0 = goff[0][o0], ro = rowoff[rw];
+      const bool ok = q < TS && (g0 | ro) >= 0;
+      v[u] = r[ok ? g0 + ro : 0];
       v[u] = ok ? v[u] : T(0);
-      pos[u] = q < TS ? S::tpos(o0, o1, o2) : -1;
+      pos[u] = q < TS ? rowpos[rw] + o0 * S::C0 : -1;
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u)
@@ -550,11 +576,8 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
   for (int q = tid; q < TS; q += nth) {
-    int o0, o1, o2;
-    S::split(q, o0, o1, o2);
-    T w = wv[0][o0] * wv[1][o1];
-    if (DIM == 3) w *= wv[2][o2];
-    dst[q] = w * tile[S::tpos(o0, o1, o2)];
+    const int o0 = q % S::L0, rw = q / S::L0;
+    dst[q] = (wv[0][o0] * roww[rw]) * tile[rowpos[rw] + o0 * S::C0];
   }
 }
 
@@ -769,7 +792,8 @@ int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* ac
 // ================================================================ dispatch (instantiated per T, DIM)
 template <class T, int DIM>
 struct Kern {
-  static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
+  // scratch: apply_big_scratch(n_elem, NP) elements (3D levels with NP = 33 only)
+  static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
                    int* nblk, hipStream_t s);
   static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
                  int npz, int waves, hipStream_t s);

@@ -12,20 +12,73 @@ namespace dgmg {
 constexpr int BIG_NP = 33;  // N_P of the largest order (P = 32)
 
 // ================================================================ operator apply
-// One block per element.  For each direction every thread owns lines of that
-// direction (as in apply_kernel); the partial sums over the directions live in
-// y itself, which only this block touches, and the barrier between directions
-// orders them: y = A x (MODE 0), y = f - A x accumulated as ((f - c0) - c1) - c2
-// so that y may alias f (MODE 1), y = A x with the block's x.y partial (MODE 2).
+// One launch per direction D (in order 0, 1, 2), one thread per line of that
+// direction, apply_lb<T>() lines per block: enough blocks to fill the chip
+// although there are few elements.  Launch D adds the direction-D terms to y
+// (launch 0 writes them); the last launch applies the mode: y = A x (MODE 0),
+// y = f - A x accumulated as ((f - c0) - c1) - c2 so that y may alias f
+// (MODE 1), y = A x with per-block partial sums of x.y (MODE 2).  The kernel
+// boundaries order the three contributions: results are deterministic.
+// Lines of direction 0 are contiguous in memory, so for D = 0 the block's
+// lines of the element and of both neighbours are staged through LDS with
+// coalesced loads (and the results stored the same way); lines of directions
+// 1 and 2 are read directly (consecutive lanes, consecutive addresses).
 // y must not alias x.
-template <class T, int NP, int MODE>
-__global__ void __launch_bounds__(256) apply_big_kernel(LevelDev<T> L, const T* __restrict__ x, const T* f,
-                                                        T* y, double* __restrict__ part, int nblk) {
-  constexpr int NE = NP * NP * NP, NLN = NP * NP, P = NP - 1;
+template <class T>
+constexpr int apply_lb() {
+  return sizeof(T) == 8 ? 64 : 128;
+}
+
+// Face data of every direction-0 line (element-major, line-major): its two end
+// values and the two end derivatives, {v_0, v_P, D0 . v, DP . v}.  The
+// block's lines are staged through LDS with coalesced loads.
+template <class T, int NP>
+__global__ void __launch_bounds__(128) apply_big_face0(LevelDev<T> L, const T* __restrict__ x,
+                                                       T* __restrict__ face, int nblk) {
+  constexpr int NE = NP * NP * NP, NLN = NP * NP, P = NP - 1, LB = apply_lb<T>();
+  constexpr int CH = (NLN + LB - 1) / LB;
+  __shared__ T sx[LB * NP], sD0[NP], sDP[NP];
+  const int b = xcd_block(nblk);
+  if (b < 0 || inactive(L.active)) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < NP; q += nth) {
+    sD0[q] = L.D[q];
+    sDP[q] = L.D[P * NP + q];
+  }
+  const int e = b / CH, c0 = (b - e * CH) * LB, t = c0 + tid;
+  const int nlines = imin(LB, NLN - c0);
+  const int64_t o = (int64_t)e * NE + (int64_t)c0 * NP;
+  for (int q = tid; q < nlines * NP; q += nth) sx[q] = x[o + q];
+  __syncthreads();
+  if (t < NLN) {
+    T d0 = 0, dP = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const T v = sx[tid * NP + k];
+      d0 += sD0[k] * v;
+      dP += sDP[k] * v;
+    }
+    T* fo = face + ((int64_t)e * NLN + t) * 4;
+    fo[0] = sx[tid * NP];
+    fo[1] = sx[tid * NP + P];
+    fo[2] = d0;
+    fo[3] = dP;
+  }
+}
+
+// face: direction-0 face data of every element (apply_big_face0), D = 0 only.
+template <class T, int NP, int MODE, int D>
+__global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* __restrict__ x, const T* f, T* y,
+                                                        const T* __restrict__ face, double* __restrict__ part,
+                                                        int nblk) {
+  constexpr int NE = NP * NP * NP, NLN = NP * NP, P = NP - 1, LB = apply_lb<T>();
+  constexpr int CH = (NLN + LB - 1) / LB;  // line chunks per element
+  constexpr int SX = D == 0 ? LB * NP : 1;
   __shared__ double red[16];
   __shared__ T sLs[NP * NP], sD0[NP], sDP[NP], srho[NP];
-  const int e = xcd_block(nblk);
-  if (e < 0 || inactive(L.active)) return;
+  __shared__ T sx[SX];
+  const int b = xcd_block(nblk);
+  if (b < 0 || inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
   for (int q = tid; q < NP; q += nth) {
@@ -33,99 +86,133 @@ __global__ void __launch_bounds__(256) apply_big_kernel(LevelDev<T> L, const T* 
     sDP[q] = L.D[P * NP + q];
     srho[q] = L.rho[q];
   }
-  __syncthreads();
+  const int e = b / CH, c0 = (b - e * CH) * LB, t = c0 + tid;
+  const int nlines = imin(LB, NLN - c0);
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   int m[3];
   m[0] = e % N1;
   m[1] = (e / N1) % N2;
   m[2] = e / (N1 * N2);
   const int64_t g0 = (int64_t)e * NE;
+  const DirDev<T> dd = L.dir[D];
+  const int estride = D == 0 ? 1 : (D == 1 ? N1 : N1 * N2);
+  const int nl = dd.nbr[2 * m[D]], nr = dd.nbr[2 * m[D] + 1];
+  const int el = e + (nl >= 0 ? nl - m[D] : 0) * estride, er = e + (nr >= 0 ? nr - m[D] : 0) * estride;
+  if constexpr (D == 0) {  // the block's lines are NP * nlines consecutive values
+    const int64_t o = g0 + (int64_t)c0 * NP;
+    for (int q = tid; q < nlines * NP; q += nth) sx[q] = x[o + q];
+  }
+  __syncthreads();
   double acc = 0.0;
-#pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
-    const DirDev<T> dd = L.dir[d];
-    const int estride = d == 0 ? 1 : (d == 1 ? N1 : N1 * N2);
-    const T* c = dd.ecoef + m[d] * ECOEF_N;
-    const int nl = dd.nbr[2 * m[d]], nr = dd.nbr[2 * m[d] + 1];
-    const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+  if (t < NLN) {
+    const T* c = dd.ecoef + m[D] * ECOEF_N;
+    const int da = D == 0 ? 1 : 0, db = D == 2 ? 1 : 2;
     const T ha = L.dir[da].ecoef[m[da] * ECOEF_N + E_HALF_DX], hb = L.dir[db].ecoef[m[db] * ECOEF_N + E_HALF_DX];
-    for (int t = tid; t < NLN; t += nth) {
-      int base, stride;
-      const int ia = t % NP, ib = t / NP;
-      if (d == 0) {
-        base = t * NP; stride = 1;
-      } else if (d == 1) {
-        base = ia + ib * NP * NP; stride = NP;
-      } else {
-        base = t; stride = NP * NP;
-      }
-      T v[NP];
-#pragma unroll
-      for (int k = 0; k < NP; ++k) v[k] = x[g0 + base + k * stride];
-      T d0 = 0, dP = 0;
+    const int ia = t % NP, ib = t / NP;
+    const int base = D == 0 ? t * NP : (D == 1 ? ia + ib * NP * NP : t);
+    const int stride = D == 0 ? 1 : (D == 1 ? NP : NP * NP);
+    T v[NP];
+    T d0 = 0, dP = 0, dL = 0, dR = 0, wlP = 0, wr0 = 0;
+    if constexpr (D == 0) {
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
+        v[k] = sx[tid * NP + k];
         d0 += sD0[k] * v[k];
         dP += sDP[k] * v[k];
       }
-      T uL = 0, dL = 0, uR = 0, dR = 0;
-      if (nl >= 0) {
-        const T* w = x + (int64_t)(e + (nl - m[d]) * estride) * NE + base;
+      const T* fl_ = face + ((int64_t)el * NLN + t) * 4;  // left neighbour: its value and derivative at i = P
+      const T* fr_ = face + ((int64_t)er * NLN + t) * 4;  // right neighbour: at i = 0
+      wlP = fl_[1];
+      dL = fl_[3];
+      wr0 = fr_[0];
+      dR = fr_[2];
+    } else {
+      const int64_t gl = (int64_t)el * NE, gr = (int64_t)er * NE;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) dL += sDP[k] * w[k * stride];
-        uL = w[P * stride];
+      for (int k = 0; k < NP; ++k) {
+        v[k] = x[g0 + base + k * stride];
+        const T wlk = x[gl + base + k * stride], wrk = x[gr + base + k * stride];
+        if (k == P) wlP = wlk;
+        if (k == 0) wr0 = wrk;
+        d0 += sD0[k] * v[k];
+        dP += sDP[k] * v[k];
+        dL += sDP[k] * wlk;
+        dR += sD0[k] * wrk;
       }
-      if (nr >= 0) {
-        const T* w = x + (int64_t)(e + (nr - m[d]) * estride) * NE + base;
+    }
+    const T ml = nl >= 0 ? T(1) : T(0), mr = nr >= 0 ? T(1) : T(0);
+    const T uL = ml * wlP, uR = mr * wr0;
+    dL *= ml;
+    dR *= mr;
+    const T jl = v[0] - uL, jr = v[P] - uR;
+    const T fl = c[E_CL] * d0 + c[E_CNL] * dL + c[E_BL] * jl;
+    const T fr = -c[E_CR] * dP - c[E_CNR] * dR + c[E_BR] * jr;
+    const T cl = c[E_CL] * jl, cr = c[E_CR] * jr, tdx = c[E_TWO_DX];
+    const T mo = ha * srho[ia] * hb * srho[ib];
+#pragma unroll 1
+    for (int i = 0; i < NP; ++i) {
+      T s = 0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) dR += sD0[k] * w[k * stride];
-        uR = w[0];
-      }
-      const T jl = v[0] - uL, jr = v[P] - uR;
-      const T fl = c[E_CL] * d0 + c[E_CNL] * dL + c[E_BL] * jl;
-      const T fr = -c[E_CR] * dP - c[E_CNR] * dR + c[E_BR] * jr;
-      const T cl = c[E_CL] * jl, cr = c[E_CR] * jr, tdx = c[E_TWO_DX];
-      const T mo = ha * srho[ia] * hb * srho[ib];
-      for (int i = 0; i < NP; ++i) {
-        T s = 0;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) s += sLs[i * NP + k] * v[k];
-        T o = tdx * s + cl * sD0[i] - cr * sDP[i];
-        if (i == 0) o += fl;
-        if (i == P) o += fr;
+      for (int k = 0; k < NP; ++k) s += sLs[i * NP + k] * v[k];
+      T o = tdx * s + cl * sD0[i] - cr * sDP[i];
+      if (i == 0) o += fl;
+      if (i == P) o += fr;
+      const T val = mo * o;
+      if constexpr (D == 0) {
+        sx[tid * NP + i] = val;  // this thread's own line: stored below, coalesced
+      } else {
         const int64_t idx = g0 + base + i * stride;
-        const T val = mo * o;
         if (MODE == 1) {
-          y[idx] = (d == 0 ? f[idx] : y[idx]) - val;
-        } else if (d == 0) {
-          y[idx] = val;
+          y[idx] = y[idx] - val;
         } else {
           const T tot = y[idx] + val;
           y[idx] = tot;
-          if (MODE == 2 && d == 2) acc += (double)v[i] * (double)tot;
+          if (MODE == 2 && D == 2) acc += (double)v[i] * (double)tot;
         }
       }
     }
-    __syncthreads();
   }
-  if (MODE == 2) {
-    const double s = block_sum(acc, red);
-    if (tid == 0) part[e] = s;
+  if constexpr (D == 0) {
+    __syncthreads();
+    const int64_t o = g0 + (int64_t)c0 * NP;
+    for (int q = tid; q < nlines * NP; q += nth) y[o + q] = MODE == 1 ? f[o + q] - sx[q] : sx[q];
+  }
+  if constexpr (MODE == 2 && D == 2) {
+    const double sum = block_sum(acc, red);
+    if (tid == 0) part[b] = sum;
   }
 }
 
+// Partial sums written by the MODE-2 apply of a large-element level.
 template <class T, int NP>
-int apply_big_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part, int* nblk_out,
-                     hipStream_t s) {
-  const int nblk = L.n_elem;
+constexpr int apply_big_blocks_per_elem() {
+  return (NP * NP + apply_lb<T>() - 1) / apply_lb<T>();
+}
+
+template <class T, int NP, int MODE>
+void apply_big_dirs(const LevelDev<T>& L, const T* x, const T* f, T* y, T* face, double* part, int nblk,
+                    hipStream_t s) {
+  dim3 grid(xcd_grid(nblk)), block(apply_lb<T>());
+  hipLaunchKernelGGL((apply_big_face0<T, NP>), grid, block, 0, s, L, x, face, nblk);
+  hipLaunchKernelGGL((apply_big_kernel<T, NP, MODE, 0>), grid, block, 0, s, L, x, f, y, face, part, nblk);
+  hipLaunchKernelGGL((apply_big_kernel<T, NP, MODE, 1>), grid, block, 0, s, L, x, f, y, face, part, nblk);
+  hipLaunchKernelGGL((apply_big_kernel<T, NP, MODE, 2>), grid, block, 0, s, L, x, f, y, face, part, nblk);
+}
+
+// Scratch elements of the large-element apply (direction-0 face data).
+inline int64_t apply_big_scratch(int n_elem, int NP) { return (int64_t)4 * n_elem * NP * NP; }
+
+template <class T, int NP>
+int apply_big_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
+                     int* nblk_out, hipStream_t s) {
+  const int nblk = L.n_elem * apply_big_blocks_per_elem<T, NP>();
   if (nblk_out) *nblk_out = nblk;
-  dim3 grid(xcd_grid(nblk)), block(256);
   if (mode == 0)
-    hipLaunchKernelGGL((apply_big_kernel<T, NP, 0>), grid, block, 0, s, L, x, f, y, part, nblk);
+    apply_big_dirs<T, NP, 0>(L, x, f, y, scratch, part, nblk, s);
   else if (mode == 1)
-    hipLaunchKernelGGL((apply_big_kernel<T, NP, 1>), grid, block, 0, s, L, x, f, y, part, nblk);
+    apply_big_dirs<T, NP, 1>(L, x, f, y, scratch, part, nblk, s);
   else
-    hipLaunchKernelGGL((apply_big_kernel<T, NP, 2>), grid, block, 0, s, L, x, f, y, part, nblk);
+    apply_big_dirs<T, NP, 2>(L, x, f, y, scratch, part, nblk, s);
   return 0;
 }
 
@@ -259,237 +346,231 @@ int transfer_big_launch(const T* J, int n_elem, bool restrict_, const T* in, T* 
 // ================================================================ FDM patch solve
 // In-place line contraction on a 2D LDS array: for each of `lines` lines v
 // (element k at tile[line * ls + k * ks]) out_j = sum_k B[k][j] v_k, B row-major
-// LEN x LEN in global memory.  Lines are the M dimension of 16x16x4 matrix-core
-// products (see Mfma), each wave owning whole blocks of 16 lines.
+// LEN x LEN in global memory, on 16x16x4 matrix-core products (see Mfma).
+// Column split for the long lines of large tiles (lines <= 64,
+// LEN <= 64, at least (LEN + 15) / 16 waves): wave w computes output columns
+// j in [16 w, 16 w + 16) for every line block, holding only its 16 x LEN slice
+// of B (LEN / 4 values per lane) and all results in registers; after a
+// barrier the waves write their columns back in place.  Every wave, active or
+// not, reaches the barrier.
 template <class T, int LEN>
-__device__ __forceinline__ void mfma_lines(T* __restrict__ tile, int lines, int ls, int ks_,
-                                           const T* __restrict__ Bm) {
-  constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16;
+__device__ __forceinline__ void mfma_lines_cols(T* __restrict__ tile, int lines, int ls, int ks_,
+                                                const T* __restrict__ Bm) {
+  constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16, MBX = 4;
   using M = Mfma<T>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int MB = (lines + 15) / 16;
-  if (wave >= MB) return;
-  T b[NB][KS];
+  const int nb = wave;
+  const bool act = nb < NB;  // wave-uniform
+  typename M::acc_t acc[MBX];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int mb = 0; mb < MBX; ++mb) acc[mb] = typename M::acc_t{0, 0, 0, 0};
+  if (act) {
+    T b[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + lk, j = nb * 16 + li;
-      b[nb][ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
-    }
-  for (int mb = wave; mb < MB; mb += nw) {
-    const int line = mb * 16 + li;
-    const bool lv = line < lines;
-    const int base = lv ? line * ls : 0;
-    typename M::acc_t acc[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename M::acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + lk;
-      const T a = (lv && k < LEN) ? tile[base + k * ks_] : T(0);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, b[nb][ks], acc[nb]);
+      b[ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int oline = mb * 16 + M::row(lk, r);
-      if (oline < lines) {
+    for (int mb = 0; mb < MBX; ++mb) {
+      if (mb < MB) {
+        const int line = mb * 16 + li;
+        const bool lv = line < lines;
+        const int base = lv ? line * ls : 0;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int j = nb * 16 + li;
-          if (j < LEN) tile[oline * ls + j * ks_] = acc[nb][r];
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + lk;
+          const T a = (lv && k < LEN) ? tile[base + k * ks_] : T(0);
+          acc[mb] = M::op(b[ks], a, acc[mb]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int mb = 0; mb < MBX; ++mb) {
+      const int line = mb * 16 + li;
+      if (mb < MB && line < lines) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = nb * 16 + M::row(lk, r);
+          if (j < LEN) tile[line * ls + j * ks_] = acc[mb][r];
         }
       }
     }
   }
 }
 
-// Contraction of length n in {NA, NL} (the two tile lengths of a patch).
-template <class T, int NA, int NL>
-__device__ __forceinline__ void mfma_lines_n(int n, T* tile, int lines, int ls, int ks_, const T* Bm) {
-  if (n == NA)
-    mfma_lines<T, NA>(tile, lines, ls, ks_, Bm);
-  else
-    mfma_lines<T, NL>(tile, lines, ls, ks_, Bm);
-}
-
-// Per-patch geometry shared by the three stages: tile lengths per grid
-// direction (len[nd] = NA, else NL), start index of the patch range and the
-// 1D tables of each direction.
-template <class T>
+// Per-patch data of the three stages; ND = the sweep normal (-1: element-
+// centred), all tile lengths compile-time: len[d] = NA for d = ND, else NL.
+template <class T, int NA, int NL, int ND>
 struct BigPatch {
-  int p[3], len[3], start[3];
+  static constexpr int L0 = ND == 0 ? NA : NL, L1 = ND == 1 ? NA : NL, L2 = ND == 2 ? NA : NL;
+  static constexpr int TS = L0 * L1 * L2;
+  int p[3];
+  const int* go[3];  // gather offsets of the patch positions (-1 outside)
   const T* w[3];
   const T* lam[3];
   const T* S[3];
   const T* ST[3];
-};
-
-template <class T, int NA, int NL>
-__device__ __forceinline__ BigPatch<T> big_patch(const LevelDev<T>& L, int nd, int pid, int npx, int npy) {
-  BigPatch<T> q;
-  q.p[0] = pid % npx;
-  q.p[1] = (pid / npx) % npy;
-  q.p[2] = pid / (npx * npy);
-  const int NP = L.NP;
+  __device__ __forceinline__ BigPatch(const LevelDev<T>& L, int pid, int npx, int npy) {
+    p[0] = pid % npx;
+    p[1] = (pid / npx) % npy;
+    p[2] = pid / (npx * npy);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const DirDev<T>& dd = L.dir[d];
-    const bool fc = d == nd;
-    q.len[d] = fc ? NA : NL;
-    q.start[d] = fc ? (q.p[d] - 1) * NP + 1 : q.p[d] * NP - L.NO;
-    q.w[d] = fc ? dd.w_fc + q.p[d] * NA : dd.w_ec + q.p[d] * NL;
-    q.lam[d] = fc ? dd.lam_fc + q.p[d] * NA : dd.lam_ec + q.p[d] * NL;
-    q.S[d] = fc ? dd.S_fc + (int64_t)q.p[d] * NA * NA : dd.S_ec + (int64_t)q.p[d] * NL * NL;
-    q.ST[d] = fc ? dd.ST_fc + (int64_t)q.p[d] * NA * NA : dd.ST_ec + (int64_t)q.p[d] * NL * NL;
+    for (int d = 0; d < 3; ++d) {
+      const DirDev<T>& dd = L.dir[d];
+      const bool fc = d == ND;
+      go[d] = fc ? dd.goff_fc + p[d] * NA : dd.goff_ec + p[d] * NL;
+      w[d] = fc ? dd.w_fc + p[d] * NA : dd.w_ec + p[d] * NL;
+      lam[d] = fc ? dd.lam_fc + p[d] * NA : dd.lam_ec + p[d] * NL;
+      S[d] = fc ? dd.S_fc + (int64_t)p[d] * NA * NA : dd.S_ec + (int64_t)p[d] * NL * NL;
+      ST[d] = fc ? dd.ST_fc + (int64_t)p[d] * NA * NA : dd.ST_ec + (int64_t)p[d] * NL * NL;
+    }
   }
-  return q;
-}
-
-// Global offset of patch position o in direction d, or -1 outside a Dirichlet domain.
-template <class T>
-__device__ __forceinline__ int64_t big_goff(const LevelDev<T>& L, const BigPatch<T>& q, int d, int o) {
-  const DirDev<T>& dd = L.dir[d];
-  const int NP = L.NP, G = dd.N * NP;
-  int g = q.start[d] + o;
-  if (dd.periodic) g = ((g % G) + G) % G;
-  if (g < 0 || g >= G) return -1;
-  const int64_t NE = (int64_t)NP * NP * NP;
-  const int64_t est = d == 0 ? NE : (d == 1 ? (int64_t)L.dir[0].N * NE : (int64_t)L.dir[0].N * L.dir[1].N * NE);
-  const int nst = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
-  const int mm = g / NP, ii = g - mm * NP;
-  return mm * est + (int64_t)ii * nst;
-}
+};
 
 constexpr int big_pitch(int n) { return n % 2 == 0 ? n + 1 : n; }
 
 // Stage A: block per (patch, o2).  Gather the plane o2 of R_s r, forward
 // transform along directions 0 and 1, store it in the patch's slot
-// (grid-natural order (o2 len1 + o1) len0 + o0).
-template <class T, int NA, int NL>
-__global__ void __launch_bounds__(256) fdm_big_a(LevelDev<T> L, int nd, const T* __restrict__ r,
-                                                 T* __restrict__ out, int npx, int npy, int npz) {
-  constexpr int NM = imax(NA, NL), PM = big_pitch(NM);
-  __shared__ T pl[NM * PM];
-  __shared__ int64_t g0[NM], g1[NM];
-  const int len2 = nd == 2 ? NA : NL;
+// (grid-natural order (o2 L1 + o1) L0 + o0).
+template <class T, int NA, int NL, int ND>
+__global__ void __launch_bounds__(256) fdm_big_a(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
+                                                 int npx, int npy, int npz) {
+  using Q = BigPatch<T, NA, NL, ND>;
+  constexpr int N0 = Q::L0, N1 = Q::L1, N2 = Q::L2, PT = big_pitch(N0);
+  __shared__ T pl[N1 * PT];
+  __shared__ int g0[N0], g1[N1];
   const int npatch = npx * npy * npz;
-  const int bid = xcd_block(npatch * len2);
+  const int bid = xcd_block(npatch * N2);
   if (bid < 0 || inactive(L.active)) return;
-  const int pid = bid / len2, o2 = bid - pid * len2;
-  const BigPatch<T> q = big_patch<T, NA, NL>(L, nd, pid, npx, npy);
-  const int n0 = q.len[0], n1 = q.len[1], pitch = big_pitch(n0);
+  const int pid = bid / N2, o2 = bid - pid * N2;
+  const Q q(L, pid, npx, npy);
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int o = tid; o < n0; o += nth) g0[o] = big_goff(L, q, 0, o);
-  for (int o = tid; o < n1; o += nth) g1[o] = big_goff(L, q, 1, o);
-  const int64_t gz = big_goff(L, q, 2, o2);
+  for (int o = tid; o < N0; o += nth) g0[o] = q.go[0][o];
+  for (int o = tid; o < N1; o += nth) g1[o] = q.go[1][o];
+  const int gz = q.go[2][o2];
   __syncthreads();
-  for (int e = tid; e < n0 * n1; e += nth) {
-    const int o1 = e / n0, o0 = e - o1 * n0;
-    const bool ok = gz >= 0 && g0[o0] >= 0 && g1[o1] >= 0;
-    pl[o1 * pitch + o0] = ok ? r[gz + g0[o0] + g1[o1]] : T(0);
+  for (int e = tid; e < N0 * N1; e += nth) {
+    const int o1 = e / N0, o0 = e - o1 * N0;
+    const int a = g0[o0], b = g1[o1];
+    const bool ok = (gz | a | b) >= 0;
+    const T v = r[ok ? gz + a + b : 0];
+    pl[o1 * PT + o0] = ok ? v : T(0);
   }
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n0, pl, n1, pitch, 1, q.S[0]);  // rows: direction 0
+  mfma_lines_cols<T, N0>(pl, N1, PT, 1, q.S[0]);  // rows: direction 0
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n1, pl, n0, 1, pitch, q.S[1]);  // columns: direction 1
+  mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.S[1]);  // columns: direction 1
   __syncthreads();
-  T* dst = out + (int64_t)pid * n0 * n1 * len2 + (int64_t)o2 * n0 * n1;
-  for (int e = tid; e < n0 * n1; e += nth) {
-    const int o1 = e / n0, o0 = e - o1 * n0;
-    dst[e] = pl[o1 * pitch + o0];
+  T* dst = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
+  for (int e = tid; e < N0 * N1; e += nth) {
+    const int o1 = e / N0, o0 = e - o1 * N0;
+    dst[e] = pl[o1 * PT + o0];
   }
 }
 
 // Stage B: block per (patch, o1).  Along direction 2: forward transform, scale
 // by 1 / (lam0 + lam1 + lam2), backward transform; in place in the slot.
-template <class T, int NA, int NL>
-__global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, int nd, T* __restrict__ out, int npx, int npy,
-                                                 int npz) {
-  constexpr int NM = imax(NA, NL), PM = big_pitch(NM);
-  __shared__ T pl[NM * PM];
-  __shared__ T l0[NM], l2[NM];
-  const int len1 = nd == 1 ? NA : NL;
+template <class T, int NA, int NL, int ND>
+__global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ out, int npx, int npy, int npz) {
+  using Q = BigPatch<T, NA, NL, ND>;
+  constexpr int N0 = Q::L0, N1 = Q::L1, N2 = Q::L2, PT = big_pitch(N0);
+  __shared__ T pl[N2 * PT];
+  __shared__ T l0[N0], l2[N2];
   const int npatch = npx * npy * npz;
-  const int bid = xcd_block(npatch * len1);
+  const int bid = xcd_block(npatch * N1);
   if (bid < 0 || inactive(L.active)) return;
-  const int pid = bid / len1, o1 = bid - pid * len1;
-  const BigPatch<T> q = big_patch<T, NA, NL>(L, nd, pid, npx, npy);
-  const int n0 = q.len[0], n1 = q.len[1], n2 = q.len[2], pitch = big_pitch(n0);
+  const int pid = bid / N1, o1 = bid - pid * N1;
+  const Q q(L, pid, npx, npy);
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int o = tid; o < n0; o += nth) l0[o] = q.lam[0][o];
-  for (int o = tid; o < n2; o += nth) l2[o] = q.lam[2][o];
+  for (int o = tid; o < N0; o += nth) l0[o] = q.lam[0][o];
+  for (int o = tid; o < N2; o += nth) l2[o] = q.lam[2][o];
   const T l1 = q.lam[1][o1];
-  T* slot = out + (int64_t)pid * n0 * n1 * n2 + (int64_t)o1 * n0;
-  const int64_t zst = (int64_t)n0 * n1;
-  for (int e = tid; e < n0 * n2; e += nth) {
-    const int o2 = e / n0, o0 = e - o2 * n0;
-    pl[o2 * pitch + o0] = slot[o2 * zst + o0];
+  T* slot = out + (int64_t)pid * Q::TS + (int64_t)o1 * N0;
+  constexpr int64_t ZST = (int64_t)N0 * N1;
+  for (int e = tid; e < N0 * N2; e += nth) {
+    const int o2 = e / N0, o0 = e - o2 * N0;
+    pl[o2 * PT + o0] = slot[o2 * ZST + o0];
   }
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n2, pl, n0, 1, pitch, q.S[2]);
+  mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.S[2]);
   __syncthreads();
-  for (int e = tid; e < n0 * n2; e += nth) {
-    const int o2 = e / n0, o0 = e - o2 * n0;
-    const int i = o2 * pitch + o0;
+  for (int e = tid; e < N0 * N2; e += nth) {
+    const int o2 = e / N0, o0 = e - o2 * N0;
+    const int i = o2 * PT + o0;
     pl[i] = pl[i] / (l0[o0] + l1 + l2[o2]);
   }
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n2, pl, n0, 1, pitch, q.ST[2]);
+  mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.ST[2]);
   __syncthreads();
-  for (int e = tid; e < n0 * n2; e += nth) {
-    const int o2 = e / n0, o0 = e - o2 * n0;
-    slot[o2 * zst + o0] = pl[o2 * pitch + o0];
+  for (int e = tid; e < N0 * N2; e += nth) {
+    const int o2 = e / N0, o0 = e - o2 * N0;
+    slot[o2 * ZST + o0] = pl[o2 * PT + o0];
   }
 }
 
 // Stage C: block per (patch, o2).  Backward transform along directions 1 and 0,
 // multiply by the weights w0 w1 w2; in place in the slot.
-template <class T, int NA, int NL>
-__global__ void __launch_bounds__(256) fdm_big_c(LevelDev<T> L, int nd, T* __restrict__ out, int npx, int npy,
-                                                 int npz) {
-  constexpr int NM = imax(NA, NL), PM = big_pitch(NM);
-  __shared__ T pl[NM * PM];
-  __shared__ T w0[NM], w1[NM];
-  const int len2 = nd == 2 ? NA : NL;
+template <class T, int NA, int NL, int ND>
+__global__ void __launch_bounds__(256) fdm_big_c(LevelDev<T> L, T* __restrict__ out, int npx, int npy, int npz) {
+  using Q = BigPatch<T, NA, NL, ND>;
+  constexpr int N0 = Q::L0, N1 = Q::L1, N2 = Q::L2, PT = big_pitch(N0);
+  __shared__ T pl[N1 * PT];
+  __shared__ T w0[N0], w1[N1];
   const int npatch = npx * npy * npz;
-  const int bid = xcd_block(npatch * len2);
+  const int bid = xcd_block(npatch * N2);
   if (bid < 0 || inactive(L.active)) return;
-  const int pid = bid / len2, o2 = bid - pid * len2;
-  const BigPatch<T> q = big_patch<T, NA, NL>(L, nd, pid, npx, npy);
-  const int n0 = q.len[0], n1 = q.len[1], pitch = big_pitch(n0);
+  const int pid = bid / N2, o2 = bid - pid * N2;
+  const Q q(L, pid, npx, npy);
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int o = tid; o < n0; o += nth) w0[o] = q.w[0][o];
-  for (int o = tid; o < n1; o += nth) w1[o] = q.w[1][o];
+  for (int o = tid; o < N0; o += nth) w0[o] = q.w[0][o];
+  for (int o = tid; o < N1; o += nth) w1[o] = q.w[1][o];
   const T w2 = q.w[2][o2];
-  T* slot = out + (int64_t)pid * n0 * n1 * len2 + (int64_t)o2 * n0 * n1;
-  for (int e = tid; e < n0 * n1; e += nth) {
-    const int o1 = e / n0, o0 = e - o1 * n0;
-    pl[o1 * pitch + o0] = slot[e];
+  T* slot = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
+  for (int e = tid; e < N0 * N1; e += nth) {
+    const int o1 = e / N0, o0 = e - o1 * N0;
+    pl[o1 * PT + o0] = slot[e];
   }
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n1, pl, n0, 1, pitch, q.ST[1]);
+  mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.ST[1]);
   __syncthreads();
-  mfma_lines_n<T, NA, NL>(n0, pl, n1, pitch, 1, q.ST[0]);
+  mfma_lines_cols<T, N0>(pl, N1, PT, 1, q.ST[0]);
   __syncthreads();
-  for (int e = tid; e < n0 * n1; e += nth) {
-    const int o1 = e / n0, o0 = e - o1 * n0;
-    slot[e] = w0[o0] * w1[o1] * w2 * pl[o1 * pitch + o0];
+  for (int e = tid; e < N0 * N1; e += nth) {
+    const int o1 = e / N0, o0 = e - o1 * N0;
+    slot[e] = w0[o0] * w1[o1] * w2 * pl[o1 * PT + o0];
   }
+}
+
+template <class T, int NA, int NL, int ND>
+void fdm_big_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, int npz, hipStream_t s) {
+  using Q = BigPatch<T, NA, NL, ND>;
+  const int npatch = npx * npy * npz;
+  hipLaunchKernelGGL((fdm_big_a<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, r, out, npx,
+                     npy, npz);
+  hipLaunchKernelGGL((fdm_big_b<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L1)), dim3(256), 0, s, L, out, npx,
+                     npy, npz);
+  hipLaunchKernelGGL((fdm_big_c<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, out, npx,
+                     npy, npz);
 }
 
 template <class T, int NA, int NL>
 int fdm_big_launch(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz, hipStream_t s) {
-  const int npatch = npx * npy * npz;
-  const int len1 = nd == 1 ? NA : NL, len2 = nd == 2 ? NA : NL;
-  hipLaunchKernelGGL((fdm_big_a<T, NA, NL>), dim3(xcd_grid(npatch * len2)), dim3(256), 0, s, L, nd, r, out, npx,
-                     npy, npz);
-  hipLaunchKernelGGL((fdm_big_b<T, NA, NL>), dim3(xcd_grid(npatch * len1)), dim3(256), 0, s, L, nd, out, npx,
-                     npy, npz);
-  hipLaunchKernelGGL((fdm_big_c<T, NA, NL>), dim3(xcd_grid(npatch * len2)), dim3(256), 0, s, L, nd, out, npx,
-                     npy, npz);
+  if (nd < 0) {
+    if constexpr (NA == NL) {
+      fdm_big_launch_nd<T, NA, NL, -1>(L, r, out, npx, npy, npz, s);
+      return 0;
+    }
+    return -4;
+  }
+  if (nd == 0) fdm_big_launch_nd<T, NA, NL, 0>(L, r, out, npx, npy, npz, s);
+  else if (nd == 1) fdm_big_launch_nd<T, NA, NL, 1>(L, r, out, npx, npy, npz, s);
+  else fdm_big_launch_nd<T, NA, NL, 2>(L, r, out, npx, npy, npz, s);
   return 0;
 }
 
