@@ -100,9 +100,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // y = A x (MODE 0), y = f - A x (MODE 1), y = A x plus per-block partial x.y (MODE 2).
 // One thread owns one line of one element per direction; neighbour traces and
 // normal derivatives are read from the neighbour's line (eq. (L:generic)).
+// Elements per block of the operator apply: lines of one direction of all of
+// them fill about DGMG_APPLY_LINES threads.
+#ifndef DGMG_APPLY_LINES
+#define DGMG_APPLY_LINES 256
+#endif
 template <int NP, int DIM>
 constexpr int apply_epb() {
-  return imax(1, 256 / ipow(NP, DIM - 1));
+  return imax(1, DGMG_APPLY_LINES / ipow(NP, DIM - 1));
 }
 template <int NP, int DIM>
 constexpr int apply_threads() {
