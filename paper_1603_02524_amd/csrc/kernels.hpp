@@ -105,6 +105,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 #ifndef DGMG_APPLY_LINES
 #define DGMG_APPLY_LINES 256
 #endif
+// Rows of the line product unrolled together (independent accumulation chains).
+#ifndef DGMG_APPLY_ROWS
+#define DGMG_APPLY_ROWS 1
+#endif
 template <int NP, int DIM>
 constexpr int apply_epb() {
   return imax(1, DGMG_APPLY_LINES / ipow(NP, DIM - 1));
@@ -201,7 +205,7 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
         mo = L.dir[da].ecoef[m[da] * ECOEF_N + E_HALF_DX] * rho[ia] *
              L.dir[db].ecoef[m[db] * ECOEF_N + E_HALF_DX] * rho[ib];
       }
-#pragma unroll 1  // one row of Ls live at a time (keeps registers for the line data)
+#pragma unroll DGMG_APPLY_ROWS  // a few rows of Ls live at a time (registers for the line data)
       for (int i = 0; i < NP; ++i) {
         T s = 0;
 #pragma unroll
