@@ -98,10 +98,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ================================================================ operator apply
 // y = A x (MODE 0), y = f - A x (MODE 1), y = A x plus per-block partial x.y (MODE 2).
-// One thread owns one line of one element per direction; neighbour traces and
-// normal derivatives are read from the neighbour's line (eq. (L:generic)).
-// Elements per block of the operator apply: lines of one direction of all of
-// them fill about DGMG_APPLY_LINES threads.
+// One thread owns one line of one element in one direction, and the lines of
+// all directions run at once (their global loads overlap instead of forming
+// one latency chain per direction).  Each node receives exactly one
+// contribution per direction, stored in that direction's LDS tile; the tiles
+// are summed in direction order at the end.  Neighbour traces and normal
+// derivatives are read from the neighbour's line (eq. (L:generic)).
+// Elements per block: lines of all directions fill about DGMG_APPLY_LINES threads.
 #ifndef DGMG_APPLY_LINES
 #define DGMG_APPLY_LINES 256
 #endif
@@ -111,11 +114,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 #endif
 template <int NP, int DIM>
 constexpr int apply_epb() {
-  return imax(1, DGMG_APPLY_LINES / ipow(NP, DIM - 1));
+  return imax(1, DGMG_APPLY_LINES / (DIM * ipow(NP, DIM - 1)));
 }
 template <int NP, int DIM>
 constexpr int apply_threads() {
-  return imin(1024, round64(apply_epb<NP, DIM>() * ipow(NP, DIM - 1)));
+  return imin(1024, round64(apply_epb<NP, DIM>() * DIM * ipow(NP, DIM - 1)));
 }
 
 template <class T, int DIM, int NP, int MODE>
@@ -125,110 +128,156 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = apply_epb<NP, DIM>();
   constexpr int P = NP - 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // only the accumulator lives in LDS; lines of x are read from global memory
+  // per-direction contribution tiles; lines of x are read from global memory
   // (each element's lines are read once per direction, then served by L1/L2)
   T* sy = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[16];
-  __shared__ T sLs[NP * NP];  // stiffness matrix: uniform-address (broadcast) reads
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
   const int e0 = blk * EPB;
   const int ne = imin(EPB, L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int64_t g0 = (int64_t)e0 * NE;
-  for (int q = tid; q < ne * NE; q += nth) sy[q] = T(0);
-  for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
-  __syncthreads();
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
-  const T* __restrict__ Ls = sLs;
-  const T* __restrict__ D0 = L.D;
-  const T* __restrict__ DP = L.D + P * NP;
+  // stiffness matrix rows: uniform addresses in the constant address space,
+  // so the row loop reads them with scalar loads into SGPR operands
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Ls = (CT*)L.Ls;
+  CT* __restrict__ D0 = (CT*)L.D;
+  CT* __restrict__ DP = (CT*)(L.D + P * NP);
   const T* __restrict__ rho = L.rho;
-#pragma unroll 1
-  for (int d = 0; d < DIM; ++d) {
-    const DirDev<T> dd = L.dir[d];
-    for (int ln = tid; ln < ne * NLN; ln += nth) {
-      const int el = ln / NLN, t = ln - el * NLN;
-      const int e = e0 + el;
-      int m[3];
-      m[0] = e % N1;
-      m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
-      m[2] = DIM == 3 ? e / (N1 * N2) : 0;
-      const int estride = d == 0 ? 1 : (d == 1 ? N1 : N1 * N2);
-      // line base and stride inside the element; indices of the other directions
-      int base, stride, ia, ib;  // ia, ib: local indices of the two other directions (in order)
-      if (d == 0) {
-        base = t * NP; stride = 1; ia = t % NP; ib = t / NP;
-      } else if (d == 1) {
-        ia = t % NP; ib = t / NP; base = ia + ib * NP * NP; stride = NP;
-      } else {
-        ia = t % NP; ib = t / NP; base = t; stride = NP * NP;
-      }
-      // neighbour lines first (unconditional loads at a valid address, masked
-      // below) so that their latency overlaps the LDS reads and the volume work
-      const int nl = dd.nbr[2 * m[d]], nr = dd.nbr[2 * m[d] + 1];
-      const T* wl = x + (int64_t)(e + (nl >= 0 ? nl - m[d] : 0) * estride) * NE + base;
-      const T* wr = x + (int64_t)(e + (nr >= 0 ? nr - m[d] : 0) * estride) * NE + base;
-      T wlv[NP], wrv[NP];
+  const int per_dir = ne * NLN;
+  // The vector the epilogue reads besides the tiles (f for the residual, x for
+  // the dot product) is fetched now, so that its latency overlaps the line work
+  // (launches use apply_threads() threads, so FQ values per thread cover the block).
+  constexpr int TH = apply_threads<NP, DIM>(), FQ = (EPB * NE + TH - 1) / TH;
+  constexpr bool PREF = MODE != 0 && NP <= 9;
+  T pre[PREF ? FQ : 1];
+  if constexpr (PREF) {
+    const T* __restrict__ src = MODE == 1 ? f : x;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        wlv[k] = wl[k * stride];
-        wrv[k] = wr[k * stride];
-      }
-      T v[NP];
-#pragma unroll
-      for (int k = 0; k < NP; ++k) v[k] = x[g0 + el * NE + base + k * stride];
-      const T* c = dd.ecoef + m[d] * ECOEF_N;
-      T d0 = 0, dP = 0, dL = 0, dR = 0;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        d0 += D0[k] * v[k];
-        dP += DP[k] * v[k];
-        dL += DP[k] * wlv[k];
-        dR += D0[k] * wrv[k];
-      }
-      const T ml = nl >= 0 ? T(1) : T(0), mr = nr >= 0 ? T(1) : T(0);
-      const T uL = ml * wlv[P], uR = mr * wrv[0];
-      dL *= ml;
-      dR *= mr;
-      const T jl = v[0] - uL, jr = v[P] - uR;
-      const T fl = c[E_CL] * d0 + c[E_CNL] * dL + c[E_BL] * jl;
-      const T fr = -c[E_CR] * dP - c[E_CNR] * dR + c[E_BR] * jr;
-      const T cl = c[E_CL] * jl, cr = c[E_CR] * jr, tdx = c[E_TWO_DX];
-      // mass factor of the other directions at this line
-      T mo;
-      if (DIM == 2) {
-        const int od = 1 - d;
-        mo = L.dir[od].ecoef[m[od] * ECOEF_N + E_HALF_DX] * rho[ia];
-      } else {
-        const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
-        mo = L.dir[da].ecoef[m[da] * ECOEF_N + E_HALF_DX] * rho[ia] *
-             L.dir[db].ecoef[m[db] * ECOEF_N + E_HALF_DX] * rho[ib];
-      }
-#pragma unroll DGMG_APPLY_ROWS  // a few rows of Ls live at a time (registers for the line data)
-      for (int i = 0; i < NP; ++i) {
-        T s = 0;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) s += Ls[i * NP + k] * v[k];
-        T o = tdx * s + cl * D0[i] - cr * DP[i];
-        if (i == 0) o += fl;
-        if (i == P) o += fr;
-        sy[el * NE + base + i * stride] += mo * o;
-      }
+    for (int j = 0; j < FQ; ++j) {
+      const int q = tid + j * nth;
+      pre[j] = q < ne * NE ? src[g0 + q] : T(0);
     }
-    __syncthreads();
   }
+  for (int q = tid; q < DIM * per_dir; q += nth) {
+    const int d = q / per_dir;
+    const int ln = q - d * per_dir;
+    const int el = ln / NLN, t = ln - el * NLN;
+    const int e = e0 + el;
+    int m[3];
+    m[0] = e % N1;
+    m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
+    m[2] = DIM == 3 ? e / (N1 * N2) : 0;
+    // per-direction fields selected per lane (the direction varies inside a wave)
+    const int md = d == 0 ? m[0] : (d == 1 ? m[1] : m[2]);
+    const int Nd = d == 0 ? N1 : (d == 1 ? N2 : L.dir[DIM - 1].N);
+    const int perd = d == 0 ? L.dir[0].periodic : (d == 1 ? L.dir[1].periodic : L.dir[DIM - 1].periodic);
+    const T* __restrict__ ecoef =
+        d == 0 ? L.dir[0].ecoef : (d == 1 ? L.dir[1].ecoef : L.dir[DIM - 1].ecoef);
+    const int estride = d == 0 ? 1 : (d == 1 ? N1 : N1 * N2);
+    // line base and stride inside the element; indices of the other directions
+    const int ia = t % NP, ib = t / NP;  // local indices of the other directions (in order)
+    int base, stride;
+    if (d == 0) {
+      base = t * NP; stride = 1;
+    } else if (d == 1) {
+      base = ia + ib * NP * NP; stride = NP;
+    } else {
+      base = t; stride = NP * NP;
+    }
+    // neighbours along d: m -/+ 1, wrapped when periodic, none (-1) at a
+    // Dirichlet end (the element neighbour table of the setup, computed here so
+    // that no load depends on another)
+    const int nl = md > 0 ? md - 1 : (perd ? Nd - 1 : -1);
+    const int nr = md < Nd - 1 ? md + 1 : (perd ? 0 : -1);
+    // All loads of the line issued as one group (up to NP = 9 a scheduling
+    // barrier keeps the compiler from spreading them over several round trips;
+    // longer lines would need more registers than that allows): own line,
+    // face coefficients, mass factors and the neighbours' lines (unconditional
+    // loads at a valid address, masked below).
+    T v[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) v[k] = x[g0 + el * NE + base + k * stride];
+    const T* c = ecoef + md * ECOEF_N;
+    const T c_two_dx = c[E_TWO_DX], c_cl = c[E_CL], c_cnl = c[E_CNL], c_bl = c[E_BL];
+    const T c_cr = c[E_CR], c_cnr = c[E_CNR], c_br = c[E_BR];
+    const T ra = rho[ia], rb = DIM == 3 ? rho[ib] : T(1);
+    T ha, hb;  // half element sizes of the other directions
+    if (DIM == 2) {
+      ha = d == 0 ? L.dir[1].ecoef[m[1] * ECOEF_N + E_HALF_DX] : L.dir[0].ecoef[m[0] * ECOEF_N + E_HALF_DX];
+      hb = T(1);
+    } else {
+      const T h0 = L.dir[0].ecoef[m[0] * ECOEF_N + E_HALF_DX];
+      const T h1 = L.dir[1].ecoef[m[1] * ECOEF_N + E_HALF_DX];
+      const T h2 = L.dir[DIM - 1].ecoef[m[2] * ECOEF_N + E_HALF_DX];
+      ha = d == 0 ? h1 : h0;
+      hb = d == 2 ? h1 : h2;
+    }
+    const T* wl = x + (int64_t)(e + (nl >= 0 ? nl - md : 0) * estride) * NE + base;
+    const T* wr = x + (int64_t)(e + (nr >= 0 ? nr - md : 0) * estride) * NE + base;
+    T wlv[NP], wrv[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      wlv[k] = wl[k * stride];
+      wrv[k] = wr[k * stride];
+    }
+    if constexpr (NP <= 9) __builtin_amdgcn_sched_barrier(0);
+    T d0 = 0, dP = 0, dL = 0, dR = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      d0 += D0[k] * v[k];
+      dP += DP[k] * v[k];
+      dL += DP[k] * wlv[k];
+      dR += D0[k] * wrv[k];
+    }
+    const T ml = nl >= 0 ? T(1) : T(0), mr = nr >= 0 ? T(1) : T(0);
+    const T uL = ml * wlv[P], uR = mr * wrv[0];
+    dL *= ml;
+    dR *= mr;
+    const T jl = v[0] - uL, jr = v[P] - uR;
+    const T fl = c_cl * d0 + c_cnl * dL + c_bl * jl;
+    const T fr = -c_cr * dP - c_cnr * dR + c_br * jr;
+    const T cl = c_cl * jl, cr = c_cr * jr, tdx = c_two_dx;
+    // mass factor of the other directions at this line
+    const T mo = DIM == 2 ? ha * ra : ha * ra * hb * rb;
+    T* __restrict__ syd = sy + (d * ne + el) * NE + base;
+#pragma unroll DGMG_APPLY_ROWS  // a few rows of Ls live at a time (registers for the line data)
+    for (int i = 0; i < NP; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) s += Ls[__builtin_amdgcn_readfirstlane(i) * NP + k] * v[k];
+      const int iu = __builtin_amdgcn_readfirstlane(i);
+      T o = tdx * s + cl * D0[iu] - cr * DP[iu];
+      if (i == 0) o += fl;
+      if (i == P) o += fr;
+      syd[i * stride] = mo * o;
+    }
+  }
+  __syncthreads();
   double acc = 0.0;
-  for (int q = tid; q < ne * NE; q += nth) {
-    const T val = sy[q];
+  const int dstride = ne * NE;
+  auto out = [&](int q, T other) {
+    T val = sy[q] + sy[dstride + q];
+    if (DIM == 3) val += sy[2 * dstride + q];
     if (MODE == 0) {
       y[g0 + q] = val;
     } else if (MODE == 1) {
-      y[g0 + q] = f[g0 + q] - val;
+      y[g0 + q] = other - val;
     } else {
       y[g0 + q] = val;
-      acc += (double)x[g0 + q] * (double)val;
+      acc += (double)other * (double)val;
     }
+  };
+  if constexpr (PREF) {
+#pragma unroll
+    for (int j = 0; j < FQ; ++j) {
+      const int q = tid + j * nth;
+      if (q < ne * NE) out(q, pre[j]);
+    }
+  } else {
+    for (int q = tid; q < ne * NE; q += nth) out(q, MODE == 1 ? f[g0 + q] : (MODE == 2 ? x[g0 + q] : T(0)));
   }
   if (MODE == 2) {
     const double s = block_sum(acc, red);
@@ -241,9 +290,9 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
                  int* nblk_out, hipStream_t s) {
   constexpr int NE = ipow(NP, DIM), EPB = apply_epb<NP, DIM>(), TH = apply_threads<NP, DIM>();
   const int nblk = (L.n_elem + EPB - 1) / EPB;
-  const size_t shm = (size_t)EPB * NE * sizeof(T);
   if (nblk_out) *nblk_out = nblk;
   dim3 grid(xcd_grid(nblk)), block(TH);
+  const size_t shm = (size_t)DIM * EPB * NE * sizeof(T);
   if (mode == 0) {
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 0>), grid, block, shm, s, L, x, f, y, part, nblk);
