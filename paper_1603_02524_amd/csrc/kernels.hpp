@@ -472,6 +472,55 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restri
   fdm_pass<T, NA, NL, DIM, TD, Post>(tile, B, post);
 }
 
+// VALU form of a contraction pass: one line per thread, out_j = sum_k B[k][j] v_k,
+// reading BT = B^T (row-major, so the coefficients of one output are one
+// contiguous row) through scalar loads: the matrix is uniform over the block.
+// Exact line lengths: FP64 vector FMA and FP64 MFMA have the same peak rate on
+// gfx950, and the matrix-core form pads lengths like 13 to 16 in both the K
+// and N dimensions (66 % useful work), so short lateral lines are cheaper here.
+// Same post(line, j, value) contract as fdm_pass.
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
+__device__ __forceinline__ void fdm_pass_valu(T* __restrict__ tile, const T* __restrict__ BTm,
+                                              Post post = Post()) {
+  constexpr int NAP = fdm_pitch<NA>();
+  constexpr int LEN = TD == 0 ? NA : NL;
+  constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
+  constexpr int STRIDE = TD == 0 ? 1 : (TD == 1 ? NAP : NAP * NL);
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ BT = (CT*)BTm;
+  for (int line = threadIdx.x; line < LINES; line += blockDim.x) {
+    const int base = fdm_line_base<NA, NL, TD>(line);
+    T v[LEN];
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) v[k] = tile[base + k * STRIDE];
+#pragma unroll 1  // one row of BT in SGPRs at a time
+    for (int j = 0; j < LEN; ++j) {
+      const int ju = __builtin_amdgcn_readfirstlane(j);
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < LEN; ++k) acc += BT[ju * LEN + k] * v[k];
+      tile[base + j * STRIDE] = post(line, j, acc);
+    }
+  }
+}
+
+// Contraction pass of tile dimension TD on the unit that suits its length:
+// lines up to DGMG_FDM_VALU_MAXLEN long go to the VALU (the matrix-core form
+// would pad a length-9 line to 12 x 16, 42 % useful work), longer ones to the
+// matrix cores (measured on the box: length 13 lateral passes on the VALU made
+// the 16 x 13 x 13 patch solve 9 % slower, every pass on the VALU 35 %).
+#ifndef DGMG_FDM_VALU_MAXLEN
+#define DGMG_FDM_VALU_MAXLEN 9
+#endif
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
+__device__ __forceinline__ void fdm_pass_any(T* __restrict__ tile, const T* __restrict__ Bm,
+                                             const T* __restrict__ BTm, Post post = Post()) {
+  constexpr int LEN = TD == 0 ? NA : NL;
+  constexpr bool VALU = LEN <= DGMG_FDM_VALU_MAXLEN;
+  if constexpr (VALU) fdm_pass_valu<T, NA, NL, DIM, TD, Post>(tile, BTm, post);
+  else fdm_pass<T, NA, NL, DIM, TD, Post>(tile, Bm, post);
+}
+
 // Tile geometry of one sweep kind, all compile-time: ND = normal direction of a
 // face-centred patch (-1: element-centred).  Grid-natural order has direction 0
 // fastest with lengths L0, L1, L2; the LDS tile keeps the normal direction
@@ -611,25 +660,25 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     if (DIM == 3) den += lv[S::gd(2)][j];
     return v / den;
   };
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, F0); else fdm_pass<T, NA, NL, DIM, 0>(tile, fwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, fwd[0], bwd[0]);
   __syncthreads();
   if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, fwd[1], bwd[1]);
     __syncthreads();
     if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, F2, scale);
-    else fdm_pass<T, NA, NL, DIM, 2>(tile, fwd[2], scale);
+    else fdm_pass_any<T, NA, NL, DIM, 2>(tile, fwd[2], bwd[2], scale);
   } else {
     if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1, scale);
-    else fdm_pass<T, NA, NL, DIM, 1>(tile, fwd[1], scale);
+    else fdm_pass_any<T, NA, NL, DIM, 1>(tile, fwd[1], bwd[1], scale);
   }
   __syncthreads();
   if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, B2); else fdm_pass<T, NA, NL, DIM, 2>(tile, bwd[2]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, B2); else fdm_pass_any<T, NA, NL, DIM, 2>(tile, bwd[2], fwd[2]);
     __syncthreads();
   }
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, B1); else fdm_pass<T, NA, NL, DIM, 1>(tile, bwd[1]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, B1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, bwd[1], fwd[1]);
   __syncthreads();
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, B0); else fdm_pass<T, NA, NL, DIM, 0>(tile, bwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, bwd[0], fwd[0]);
   __syncthreads();
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
