@@ -479,6 +479,17 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restri
 // gfx950, and the matrix-core form pads lengths like 13 to 16 in both the K
 // and N dimensions (66 % useful work), so short lateral lines are cheaper here.
 // Same post(line, j, value) contract as fdm_pass.
+// Rows of the matrix per step of the VALU pass: the largest divisor R of LEN
+// with R LEN values within 32 FP64 (64 FP32) SGPR pairs / SGPRs.
+template <class T, int LEN>
+constexpr int fdm_valu_rows() {
+  constexpr int cap = sizeof(T) == 8 ? 32 : 64;
+  int best = 1;
+  for (int r = 1; r <= LEN; ++r)
+    if (LEN % r == 0 && r * LEN <= cap) best = r;
+  return best;
+}
+
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
 __device__ __forceinline__ void fdm_pass_valu(T* __restrict__ tile, const T* __restrict__ BTm,
                                               Post post = Post()) {
@@ -488,18 +499,26 @@ __device__ __forceinline__ void fdm_pass_valu(T* __restrict__ tile, const T* __r
   constexpr int STRIDE = TD == 0 ? 1 : (TD == 1 ? NAP : NAP * NL);
   using CT = const __attribute__((address_space(4))) T;
   CT* __restrict__ BT = (CT*)BTm;
+  constexpr int R = fdm_valu_rows<T, LEN>();
   for (int line = threadIdx.x; line < LINES; line += blockDim.x) {
     const int base = fdm_line_base<NA, NL, TD>(line);
     T v[LEN];
 #pragma unroll
     for (int k = 0; k < LEN; ++k) v[k] = tile[base + k * STRIDE];
-#pragma unroll 1  // one row of BT in SGPRs at a time
-    for (int j = 0; j < LEN; ++j) {
-      const int ju = __builtin_amdgcn_readfirstlane(j);
-      T acc = 0;
+    // R rows of BT per step: R independent accumulation chains, one scalar
+    // load group per step, at most 32 FP64 (64 FP32) matrix values in SGPRs
+#pragma unroll 1
+    for (int j0 = 0; j0 < LEN; j0 += R) {
+      const int ju = __builtin_amdgcn_readfirstlane(j0);
+      T acc[R];
 #pragma unroll
-      for (int k = 0; k < LEN; ++k) acc += BT[ju * LEN + k] * v[k];
-      tile[base + j * STRIDE] = post(line, j, acc);
+      for (int r = 0; r < R; ++r) acc[r] = 0;
+#pragma unroll
+      for (int k = 0; k < LEN; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += BT[(ju + r) * LEN + k] * v[k];
+#pragma unroll
+      for (int r = 0; r < R; ++r) tile[base + (j0 + r) * STRIDE] = post(line, j0 + r, acc[r]);
     }
   }
 }
