@@ -391,7 +391,9 @@ struct BOp {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int k = 4 * ks + lk, j = nb * 16 + li;
-        b[nb][ks] = (k < LEN && j < LEN) ? Bm[k * LEN + j] : T(0);
+        // unconditional load at a valid index, zero outside the matrix (no branch)
+        const T v = Bm[imin(k, LEN - 1) * LEN + imin(j, LEN - 1)];
+        b[nb][ks] = (k < LEN && j < LEN) ? v : T(0);
       }
   }
 };
@@ -408,9 +410,14 @@ struct NoPost {
 
 // post(line, j, value) maps each result before it is stored (e.g. the
 // eigenvalue scaling fused into the last forward pass).
+// No lane-dependent branches: loads past the end of a line or of the line set
+// read a valid element instead (the matrix operand is zero for k >= LEN, and
+// results of lines past the set are discarded), and stores of rows j >= LEN or
+// of lines past the set go to the lane's slot of `trash` (64 values, dead
+// storage) instead of being masked.
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
-__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD == 0 ? NA : NL>& B,
-                                         Post post = Post()) {
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ trash,
+                                         const BOp<T, TD == 0 ? NA : NL>& B, Post post = Post()) {
   // Product D = B^T V^T: the A operand is B^T (held as B.b), the B operand the
   // lines; lane (li, lk) then owns output column li = its own line, rows
   // j = 16 nb + row(lk, r), so results go back along the line it loaded.
@@ -421,17 +428,21 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
   constexpr int KS = BOp<T, LEN>::KS, NB = BOp<T, LEN>::NB, MB = (LINES + 15) / 16;
   constexpr int MBLK = DGMG_FDM_MBLK;
   using M = Mfma<T>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // the wave index is uniform over the wave: keeping it scalar makes the block
+  // loop a scalar loop
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int mb0 = wave; mb0 < MB; mb0 += MBLK * nw) {
-    int base[MBLK];
+    int base[MBLK], lc[MBLK];
     bool lv[MBLK], act[MBLK];
 #pragma unroll
     for (int t = 0; t < MBLK; ++t) {
       const int mb = mb0 + t * nw, line = mb * 16 + li;
       act[t] = mb < MB;  // wave-uniform
       lv[t] = act[t] && line < LINES;
-      base[t] = lv[t] ? fdm_line_base<NA, NL, TD>(line) : 0;
+      lc[t] = imin(line, LINES - 1);
+      base[t] = fdm_line_base<NA, NL, TD>(lc[t]);
     }
     typename M::acc_t acc[MBLK][NB];
 #pragma unroll
@@ -440,10 +451,10 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
       for (int nb = 0; nb < NB; ++nb) acc[t][nb] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + lk;
+      const int k = imin(4 * ks + lk, LEN - 1);
       T a[MBLK];
 #pragma unroll
-      for (int t = 0; t < MBLK; ++t) a[t] = (lv[t] && k < LEN) ? tile[base[t] + k * STRIDE] : T(0);
+      for (int t = 0; t < MBLK; ++t) a[t] = act[t] ? tile[base[t] + k * STRIDE] : T(0);
 #pragma unroll
       for (int t = 0; t < MBLK; ++t)
         if (act[t])
@@ -452,24 +463,27 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const BOp<T, TD =
     }
 #pragma unroll
     for (int t = 0; t < MBLK; ++t) {
-      if (!lv[t]) continue;
-      const int line = (mb0 + t * nw) * 16 + li;
+      if (!act[t]) continue;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = nb * 16 + M::row(lk, r);
-          if (j < LEN) tile[base[t] + j * STRIDE] = post(line, j, acc[t][nb][r]);
+          const bool ok = lv[t] && j < LEN;
+          const int jc = imin(j, LEN - 1);
+          T* dst = ok ? tile + base[t] + jc * STRIDE : trash + lane;
+          *dst = post(lc[t], jc, acc[t][nb][r]);
         }
     }
   }
 }
 
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
-__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, const T* __restrict__ Bm, Post post = Post()) {
+__device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ trash, const T* __restrict__ Bm,
+                                         Post post = Post()) {
   BOp<T, TD == 0 ? NA : NL> B;
   B.load(Bm);
-  fdm_pass<T, NA, NL, DIM, TD, Post>(tile, B, post);
+  fdm_pass<T, NA, NL, DIM, TD, Post>(tile, trash, B, post);
 }
 
 // VALU form of a contraction pass: one line per thread, out_j = sum_k B[k][j] v_k,
@@ -532,12 +546,12 @@ __device__ __forceinline__ void fdm_pass_valu(T* __restrict__ tile, const T* __r
 #define DGMG_FDM_VALU_MAXLEN 9
 #endif
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
-__device__ __forceinline__ void fdm_pass_any(T* __restrict__ tile, const T* __restrict__ Bm,
+__device__ __forceinline__ void fdm_pass_any(T* __restrict__ tile, T* __restrict__ trash, const T* __restrict__ Bm,
                                              const T* __restrict__ BTm, Post post = Post()) {
   constexpr int LEN = TD == 0 ? NA : NL;
   constexpr bool VALU = LEN <= DGMG_FDM_VALU_MAXLEN;
   if constexpr (VALU) fdm_pass_valu<T, NA, NL, DIM, TD, Post>(tile, BTm, post);
-  else fdm_pass<T, NA, NL, DIM, TD, Post>(tile, Bm, post);
+  else fdm_pass<T, NA, NL, DIM, TD, Post>(tile, trash, Bm, post);
 }
 
 // Tile geometry of one sweep kind, all compile-time: ND = normal direction of a
@@ -582,7 +596,10 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   __shared__ int goff[3][NMAX];  // offsets into the level vector (< 2^31 unknowns), -1 outside
   __shared__ T wv[3][NMAX];
   __shared__ T lv[3][NMAX];
-  __shared__ int rowoff[S::NROW], rowpos[S::NROW];
+  // rowoff is dead once the gather is done: the contraction passes use it as
+  // their store trash (64 values)
+  __shared__ __align__(8) int rowoff[imax(S::NROW, 64 * (int)sizeof(T) / (int)sizeof(int))];
+  __shared__ int rowpos[S::NROW];
   __shared__ T roww[S::NROW];
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   const int pid = xcd_block(npatch);
@@ -671,6 +688,7 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
       if (pos[u] >= 0) tile[pos[u]] = v[u];
   }
   __syncthreads();
+  T* trash = reinterpret_cast<T*>(rowoff);
   // the last forward pass divides each result by the sum of the 1D eigenvalues
   // of its tile position: line = a + NA l1 (3D; a in 2D), j = l2 (3D; l1 in 2D)
   const auto scale = [&](int line, int j, T v) -> T {
@@ -679,25 +697,25 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     if (DIM == 3) den += lv[S::gd(2)][j];
     return v / den;
   };
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, fwd[0], bwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, fwd[0], bwd[0]);
   __syncthreads();
   if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, fwd[1], bwd[1]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, F1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1]);
     __syncthreads();
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, F2, scale);
-    else fdm_pass_any<T, NA, NL, DIM, 2>(tile, fwd[2], bwd[2], scale);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, trash, F2, scale);
+    else fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, fwd[2], bwd[2], scale);
   } else {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, F1, scale);
-    else fdm_pass_any<T, NA, NL, DIM, 1>(tile, fwd[1], bwd[1], scale);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, F1, scale);
+    else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1], scale);
   }
   __syncthreads();
   if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, B2); else fdm_pass_any<T, NA, NL, DIM, 2>(tile, bwd[2], fwd[2]);
+    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, trash, B2); else fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, bwd[2], fwd[2]);
     __syncthreads();
   }
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, B1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, bwd[1], fwd[1]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, B1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, bwd[1], fwd[1]);
   __syncthreads();
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, bwd[0], fwd[0]);
+  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, bwd[0], fwd[0]);
   __syncthreads();
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
