@@ -307,6 +307,33 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
 }
 
 // ================================================================ FDM patch solve
+// Patch-solve code choices: the eigenvalue scaling by reciprocal estimate and
+// Newton steps instead of IEEE division, and for rows exactly 16 long the
+// gather / scatter in 16-lane row groups (no index division, per-column table
+// values in registers).
+#ifndef DGMG_FDM_DIV_NR
+#define DGMG_FDM_DIV_NR 1
+#endif
+#ifndef DGMG_FDM_GATHER2D
+#define DGMG_FDM_GATHER2D 1
+#endif
+
+// v / d for d > 0 of moderate magnitude (sums of patch eigenvalues): hardware
+// reciprocal estimate, Newton-Raphson refinement of 1/d, then one residual
+// correction of the quotient (within an ulp or two of the rounded quotient).
+__device__ __forceinline__ double div_nr(double v, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double q = v * r;
+  return fma(fma(-d, q, v), r, q);
+}
+__device__ __forceinline__ float div_nr(float v, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(fmaf(-d, r, 1.0f), r, r);
+  const float q = v * r;
+  return fmaf(fmaf(-d, q, v), r, q);
+}
 // One patch per block.  The LDS tile keeps the normal direction fastest:
 // tile[(l2 * NL + l1) * NAP + a], NAP = NA rounded up to an odd pitch so that
 // the lines of the fastest pass spread over the LDS banks.  NA = 2P for a
@@ -669,23 +696,50 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   // gather R_s r in grid-natural order (coalesced global reads); GU loads are
   // issued before their LDS stores; positions outside a Dirichlet domain read
   // r[0] and store 0
-  for (int q0 = tid; q0 < TS; q0 += GU * nth) {
-    T v[GU];
-    int pos[GU];
+  constexpr bool G2D = DGMG_FDM_GATHER2D && S::L0 == 16;  // shorter rows would idle lanes (measured slower)
+  if constexpr (G2D) {
+    // lanes in groups of 16 along direction 0 (o0 = tid % 16), rows in steps of nth / 16
+    const int o0 = tid & 15, rstep = nth >> 4;
+    const bool colok = o0 < S::L0;
+    const int oc = colok ? o0 : 0;
+    const int g0 = goff[0][oc], pc = oc * S::C0;
+    for (int rw0 = tid >> 4; rw0 < S::NROW; rw0 += GU * rstep) {
+      T v[GU];
+      int pos[GU];
 #pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const int q = q0 + u * nth;
-      const int qq = q < TS ? q : 0;
-      const int o0 = qq % S::L0, rw = qq / S::L0;
-      const int g0 = goff[0][o0], ro = rowoff[rw];
-      const bool ok = q < TS && (g0 | ro) >= 0;
-      v[u] = r[ok ? g0 + ro : 0];
-      v[u] = ok ? v[u] : T(0);
-      pos[u] = q < TS ? rowpos[rw] + o0 * S::C0 : -1;
+      for (int u = 0; u < GU; ++u) {
+        const int rw = rw0 + u * rstep;
+        const bool in = colok && rw < S::NROW;
+        const int rwc = rw < S::NROW ? rw : 0;
+        const int ro = rowoff[rwc];
+        const bool ok = in && (g0 | ro) >= 0;
+        v[u] = r[ok ? g0 + ro : 0];
+        v[u] = ok ? v[u] : T(0);
+        pos[u] = in ? rowpos[rwc] + pc : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < GU; ++u)
+        if (pos[u] >= 0) tile[pos[u]] = v[u];
     }
+  } else {
+    for (int q0 = tid; q0 < TS; q0 += GU * nth) {
+      T v[GU];
+      int pos[GU];
 #pragma unroll
-    for (int u = 0; u < GU; ++u)
-      if (pos[u] >= 0) tile[pos[u]] = v[u];
+      for (int u = 0; u < GU; ++u) {
+        const int q = q0 + u * nth;
+        const int qq = q < TS ? q : 0;
+        const int o0 = qq % S::L0, rw = qq / S::L0;
+        const int g0 = goff[0][o0], ro = rowoff[rw];
+        const bool ok = q < TS && (g0 | ro) >= 0;
+        v[u] = r[ok ? g0 + ro : 0];
+        v[u] = ok ? v[u] : T(0);
+        pos[u] = q < TS ? rowpos[rw] + o0 * S::C0 : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < GU; ++u)
+        if (pos[u] >= 0) tile[pos[u]] = v[u];
+    }
   }
   __syncthreads();
   T* trash = reinterpret_cast<T*>(rowoff);
@@ -695,7 +749,8 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     const int a = line % NA;
     T den = lv[S::gd(0)][a] + lv[S::gd(1)][DIM == 3 ? line / NA : j];
     if (DIM == 3) den += lv[S::gd(2)][j];
-    return v / den;
+    if constexpr (DGMG_FDM_DIV_NR) return div_nr(v, den);
+    else return v / den;
   };
   if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, fwd[0], bwd[0]);
   __syncthreads();
@@ -719,9 +774,18 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   __syncthreads();
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
-  for (int q = tid; q < TS; q += nth) {
-    const int o0 = q % S::L0, rw = q / S::L0;
-    dst[q] = (wv[0][o0] * roww[rw]) * tile[rowpos[rw] + o0 * S::C0];
+  if constexpr (G2D) {
+    const int o0 = tid & 15, rstep = nth >> 4;
+    if (o0 < S::L0) {
+      const T w0 = wv[0][o0];
+      const int pc = o0 * S::C0;
+      for (int rw = tid >> 4; rw < S::NROW; rw += rstep) dst[rw * S::L0 + o0] = (w0 * roww[rw]) * tile[rowpos[rw] + pc];
+    }
+  } else {
+    for (int q = tid; q < TS; q += nth) {
+      const int o0 = q % S::L0, rw = q / S::L0;
+      dst[q] = (wv[0][o0] * roww[rw]) * tile[rowpos[rw] + o0 * S::C0];
+    }
   }
 }
 
