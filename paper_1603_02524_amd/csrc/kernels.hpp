@@ -121,16 +121,52 @@ constexpr int apply_threads() {
   return imin(1024, round64(apply_epb<NP, DIM>() * DIM * ipow(NP, DIM - 1)));
 }
 
+// A kernel-argument pointer pinned in scalar registers: selecting between such
+// values per lane stays a register select instead of becoming a per-lane load
+// from the argument segment (which would make the loads behind it dependent).
+template <class P>
+__device__ __forceinline__ P* sgpr_ptr(P* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
+}
+
+// Own elements staged in LDS (coalesced loads) when the tiles are small: the
+// lines of the block's own elements are then read from LDS and only the
+// neighbours' lines from global memory.  Lines along direction 1 are strided
+// in memory (a load touches one cache line per lane), so this removes the
+// costliest third of the line loads.
+template <int NP, int DIM>
+constexpr bool apply_stage_own() {
+  return NP <= 9 && apply_epb<NP, DIM>() * DIM * ipow(NP, DIM - 1) <= 1024;
+}
+template <class T, int DIM, int NP>
+constexpr size_t apply_shmem() {
+  return (size_t)(DIM + (apply_stage_own<NP, DIM>() ? 1 : 0)) * apply_epb<NP, DIM>() * ipow(NP, DIM) * sizeof(T);
+}
+
+// Everything one line needs besides its own values: indices, the neighbours'
+// lines (masks ml, mr), the face coefficients and the mass factor.
+template <class T, int NP>
+struct ApplyLine {
+  int d, el, base, stride;
+  T ml, mr, mo;
+  T c_two_dx, c_cl, c_cnl, c_bl, c_cr, c_cnr, c_br;
+  T wlv[NP], wrv[NP];
+};
+
 template <class T, int DIM, int NP, int MODE>
 __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __restrict__ x,
                                                      const T* __restrict__ f, T* __restrict__ y,
                                                      double* __restrict__ part, int nblk) {
   constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = apply_epb<NP, DIM>();
   constexpr int P = NP - 1;
+  constexpr bool STAGE = apply_stage_own<NP, DIM>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // per-direction contribution tiles; lines of x are read from global memory
-  // (each element's lines are read once per direction, then served by L1/L2)
+  // per-direction contribution tiles, then (STAGE) the block's own elements
   T* sy = reinterpret_cast<T*>(smem_raw);
+  T* sx = sy + DIM * EPB * NE;
   __shared__ double red[16];
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
@@ -147,6 +183,18 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   CT* __restrict__ DP = (CT*)(L.D + P * NP);
   const T* __restrict__ rho = L.rho;
   const int per_dir = ne * NLN;
+  // per-direction kernel arguments in scalar registers; the per-lane choice
+  // below is arithmetic with 0/1 flags (a select chain over them gets turned
+  // into a small scratch array or into per-lane loads of the arguments)
+  using GT = const __attribute__((address_space(1))) T;  // global memory
+  GT* ec0 = (GT*)sgpr_ptr(L.dir[0].ecoef);
+  GT* ec1 = (GT*)sgpr_ptr(L.dir[1].ecoef);
+  GT* ec2 = (GT*)sgpr_ptr(L.dir[DIM - 1].ecoef);
+  const int64_t eo1 = ec1 - ec0, eo2 = ec2 - ec0;
+  const int per0 = __builtin_amdgcn_readfirstlane(L.dir[0].periodic);
+  const int per1 = __builtin_amdgcn_readfirstlane(L.dir[1].periodic);
+  const int per2 = __builtin_amdgcn_readfirstlane(L.dir[DIM - 1].periodic);
+  const int N3 = __builtin_amdgcn_readfirstlane(L.dir[DIM - 1].N);
   // The vector the epilogue reads besides the tiles (f for the residual, x for
   // the dot product) is fetched now, so that its latency overlaps the line work
   // (launches use apply_threads() threads, so FQ values per thread cover the block).
@@ -161,7 +209,10 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       pre[j] = q < ne * NE ? src[g0 + q] : T(0);
     }
   }
-  for (int q = tid; q < DIM * per_dir; q += nth) {
+  // Loads of line q (all issued as one group): neighbours' lines (unconditional
+  // loads at a valid address, masked later), coefficients, mass factors and,
+  // unless staged, the own line into v.
+  auto prep = [&](int q, ApplyLine<T, NP>& A, T* v, bool own) {
     const int d = q / per_dir;
     const int ln = q - d * per_dir;
     const int el = ln / NLN, t = ln - el * NLN;
@@ -170,13 +221,13 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
     m[0] = e % N1;
     m[1] = DIM == 3 ? (e / N1) % N2 : e / N1;
     m[2] = DIM == 3 ? e / (N1 * N2) : 0;
-    // per-direction fields selected per lane (the direction varies inside a wave)
-    const int md = d == 0 ? m[0] : (d == 1 ? m[1] : m[2]);
-    const int Nd = d == 0 ? N1 : (d == 1 ? N2 : L.dir[DIM - 1].N);
-    const int perd = d == 0 ? L.dir[0].periodic : (d == 1 ? L.dir[1].periodic : L.dir[DIM - 1].periodic);
-    const T* __restrict__ ecoef =
-        d == 0 ? L.dir[0].ecoef : (d == 1 ? L.dir[1].ecoef : L.dir[DIM - 1].ecoef);
-    const int estride = d == 0 ? 1 : (d == 1 ? N1 : N1 * N2);
+    // per-direction fields chosen per lane (the direction varies inside a wave)
+    const int f0 = d == 0, f1 = d == 1, f2 = d == 2;
+    const int md = f0 * m[0] + f1 * m[1] + f2 * m[2];
+    const int Nd = f0 * N1 + f1 * N2 + f2 * N3;
+    const int perd = f0 * per0 + f1 * per1 + f2 * per2;
+    GT* __restrict__ ecoef = ec0 + (f1 * eo1 + f2 * eo2);
+    const int estride = f0 + f1 * N1 + f2 * (N1 * N2);
     // line base and stride inside the element; indices of the other directions
     const int ia = t % NP, ib = t / NP;  // local indices of the other directions (in order)
     int base, stride;
@@ -187,62 +238,69 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
     } else {
       base = t; stride = NP * NP;
     }
+    A.d = d;
+    A.el = el;
+    A.base = base;
+    A.stride = stride;
     // neighbours along d: m -/+ 1, wrapped when periodic, none (-1) at a
     // Dirichlet end (the element neighbour table of the setup, computed here so
     // that no load depends on another)
     const int nl = md > 0 ? md - 1 : (perd ? Nd - 1 : -1);
     const int nr = md < Nd - 1 ? md + 1 : (perd ? 0 : -1);
-    // All loads of the line issued as one group (up to NP = 9 a scheduling
-    // barrier keeps the compiler from spreading them over several round trips;
-    // longer lines would need more registers than that allows): own line,
-    // face coefficients, mass factors and the neighbours' lines (unconditional
-    // loads at a valid address, masked below).
-    T v[NP];
+    A.ml = nl >= 0 ? T(1) : T(0);
+    A.mr = nr >= 0 ? T(1) : T(0);
+    if (own) {
 #pragma unroll
-    for (int k = 0; k < NP; ++k) v[k] = x[g0 + el * NE + base + k * stride];
-    const T* c = ecoef + md * ECOEF_N;
-    const T c_two_dx = c[E_TWO_DX], c_cl = c[E_CL], c_cnl = c[E_CNL], c_bl = c[E_BL];
-    const T c_cr = c[E_CR], c_cnr = c[E_CNR], c_br = c[E_BR];
+      for (int k = 0; k < NP; ++k) v[k] = x[g0 + el * NE + base + k * stride];
+    }
+    GT* c = ecoef + md * ECOEF_N;
+    A.c_two_dx = c[E_TWO_DX];
+    A.c_cl = c[E_CL];
+    A.c_cnl = c[E_CNL];
+    A.c_bl = c[E_BL];
+    A.c_cr = c[E_CR];
+    A.c_cnr = c[E_CNR];
+    A.c_br = c[E_BR];
     const T ra = rho[ia], rb = DIM == 3 ? rho[ib] : T(1);
     T ha, hb;  // half element sizes of the other directions
     if (DIM == 2) {
-      ha = d == 0 ? L.dir[1].ecoef[m[1] * ECOEF_N + E_HALF_DX] : L.dir[0].ecoef[m[0] * ECOEF_N + E_HALF_DX];
+      ha = d == 0 ? ec1[m[1] * ECOEF_N + E_HALF_DX] : ec0[m[0] * ECOEF_N + E_HALF_DX];
       hb = T(1);
     } else {
-      const T h0 = L.dir[0].ecoef[m[0] * ECOEF_N + E_HALF_DX];
-      const T h1 = L.dir[1].ecoef[m[1] * ECOEF_N + E_HALF_DX];
-      const T h2 = L.dir[DIM - 1].ecoef[m[2] * ECOEF_N + E_HALF_DX];
+      const T h0 = ec0[m[0] * ECOEF_N + E_HALF_DX];
+      const T h1 = ec1[m[1] * ECOEF_N + E_HALF_DX];
+      const T h2 = ec2[m[2] * ECOEF_N + E_HALF_DX];
       ha = d == 0 ? h1 : h0;
       hb = d == 2 ? h1 : h2;
     }
+    // mass factor of the other directions at this line
+    A.mo = DIM == 2 ? ha * ra : ha * ra * hb * rb;
     const T* wl = x + (int64_t)(e + (nl >= 0 ? nl - md : 0) * estride) * NE + base;
     const T* wr = x + (int64_t)(e + (nr >= 0 ? nr - md : 0) * estride) * NE + base;
-    T wlv[NP], wrv[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      wlv[k] = wl[k * stride];
-      wrv[k] = wr[k * stride];
+      A.wlv[k] = wl[k * stride];
+      A.wrv[k] = wr[k * stride];
     }
-    if constexpr (NP <= 9) __builtin_amdgcn_sched_barrier(0);
+  };
+  // the line's contribution mo * (L_d-row terms) into its direction's tile
+  auto finish = [&](const ApplyLine<T, NP>& A, const T* v) {
     T d0 = 0, dP = 0, dL = 0, dR = 0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       d0 += D0[k] * v[k];
       dP += DP[k] * v[k];
-      dL += DP[k] * wlv[k];
-      dR += D0[k] * wrv[k];
+      dL += DP[k] * A.wlv[k];
+      dR += D0[k] * A.wrv[k];
     }
-    const T ml = nl >= 0 ? T(1) : T(0), mr = nr >= 0 ? T(1) : T(0);
-    const T uL = ml * wlv[P], uR = mr * wrv[0];
-    dL *= ml;
-    dR *= mr;
+    const T uL = A.ml * A.wlv[P], uR = A.mr * A.wrv[0];
+    dL *= A.ml;
+    dR *= A.mr;
     const T jl = v[0] - uL, jr = v[P] - uR;
-    const T fl = c_cl * d0 + c_cnl * dL + c_bl * jl;
-    const T fr = -c_cr * dP - c_cnr * dR + c_br * jr;
-    const T cl = c_cl * jl, cr = c_cr * jr, tdx = c_two_dx;
-    // mass factor of the other directions at this line
-    const T mo = DIM == 2 ? ha * ra : ha * ra * hb * rb;
-    T* __restrict__ syd = sy + (d * ne + el) * NE + base;
+    const T fl = A.c_cl * d0 + A.c_cnl * dL + A.c_bl * jl;
+    const T fr = -A.c_cr * dP - A.c_cnr * dR + A.c_br * jr;
+    const T cl = A.c_cl * jl, cr = A.c_cr * jr, tdx = A.c_two_dx;
+    T* __restrict__ syd = sy + (A.d * ne + A.el) * NE + A.base;
 #pragma unroll DGMG_APPLY_ROWS  // a few rows of Ls live at a time (registers for the line data)
     for (int i = 0; i < NP; ++i) {
       T s = 0;
@@ -252,7 +310,41 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       T o = tdx * s + cl * D0[iu] - cr * DP[iu];
       if (i == 0) o += fl;
       if (i == P) o += fr;
-      syd[i * stride] = mo * o;
+      syd[i * A.stride] = A.mo * o;
+    }
+  };
+  if constexpr (STAGE) {
+    // one line per thread (the launch covers all lines of the block)
+    constexpr int SQ = (EPB * NE + TH - 1) / TH;
+    T st[SQ];
+#pragma unroll
+    for (int j = 0; j < SQ; ++j) {
+      const int q = tid + j * nth;
+      st[j] = q < ne * NE ? x[g0 + q] : T(0);
+    }
+    const bool has = tid < DIM * per_dir;
+    ApplyLine<T, NP> A;
+    T v[NP];
+    prep(has ? tid : 0, A, v, false);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < SQ; ++j) {
+      const int q = tid + j * nth;
+      if (q < ne * NE) sx[q] = st[j];
+    }
+    __syncthreads();
+    if (has) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) v[k] = sx[A.el * NE + A.base + k * A.stride];
+      finish(A, v);
+    }
+  } else {
+    for (int q = tid; q < DIM * per_dir; q += nth) {
+      ApplyLine<T, NP> A;
+      T v[NP];
+      prep(q, A, v, true);
+      if constexpr (NP <= 9) __builtin_amdgcn_sched_barrier(0);
+      finish(A, v);
     }
   }
   __syncthreads();
@@ -292,7 +384,7 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
   const int nblk = (L.n_elem + EPB - 1) / EPB;
   if (nblk_out) *nblk_out = nblk;
   dim3 grid(xcd_grid(nblk)), block(TH);
-  const size_t shm = (size_t)DIM * EPB * NE * sizeof(T);
+  const size_t shm = apply_shmem<T, DIM, NP>();
   if (mode == 0) {
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 0>), grid, block, shm, s, L, x, f, y, part, nblk);
