@@ -201,7 +201,20 @@ __global__ void __launch_bounds__(VEC_THREADS) k_coarse_pass(CoarseDev C, int d,
   const int64_t base = q - (int64_t)m[d] * est - ii[d] * nst;
   const double* S = C.S[d];
   double s = 0.0;
-  for (int K = 0; K < G; ++K) {
+  // loads issued in groups of 8 ahead of the products (the sum keeps the order K = 0, 1, ...)
+  int K = 0;
+  for (; K + 8 <= G; K += 8) {
+    double v[8], w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = K + u;
+      v[u] = in[base + (int64_t)(k >> 1) * est + (k & 1) * nst];
+      w[u] = FWD ? S[k * G + I] : S[I * G + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += w[u] * v[u];
+  }
+  for (; K < G; ++K) {
     const double v = in[base + (int64_t)(K >> 1) * est + (K & 1) * nst];
     s += (FWD ? S[K * G + I] : S[I * G + K]) * v;
   }
@@ -568,14 +581,16 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero =
   rc = check_hip(h, "patch solve");
   if (rc) return rc;
   T* pb = (T*)h->patch;
-  rc = L.dim == 3 ? Kern<T, 3>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], h->stream)
-                  : Kern<T, 2>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], h->stream);
+  // u == 0 on entry: the overlap sum is assigned (no fill of u beforehand, no read of it)
+  rc = L.dim == 3 ? Kern<T, 3>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream)
+                  : Kern<T, 2>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no combine kernel for this order");
   return check_hip(h, "combine");
 }
 
 // `steps` smoothing steps (EA: one sweep; FA: one sweep per direction).
-// u_zero: u == 0 on entry (the first sweep then skips its residual apply).
+// u_zero: u is taken as 0 on entry, whatever it holds (the first sweep skips
+// its residual apply and assigns u); needs steps >= 1.
 template <class T>
 int k_smooth(dgmg_handle* h, int l, T* u, const T* f, int steps, T* r, bool u_zero = false) {
   for (int s = 0; s < steps; ++s) {
@@ -686,11 +701,12 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
     const int base = which == 0 ? h->opts.ns_pre : h->opts.ns_post;
     return var ? base << (L - l) : base;
   };
-  k_fill_v<T>(h, u[L], h->lv[L].n_dof);
   for (int l = L; l >= 1; --l) {
-    if (l < L) k_fill_v<T>(h, u[l], h->lv[l].n_dof);
+    // with pre-smoothing its first sweep assigns u (u_zero); without, u starts from zero
+    const bool pre = ns(l, 0) > 0;
+    if (!pre) k_fill_v<T>(h, u[l], h->lv[l].n_dof);
     T* rl = (T*)h->buf[l].r;
-    int rc = k_smooth<T>(h, l, u[l], f[l], ns(l, 0), rl, true);
+    int rc = k_smooth<T>(h, l, u[l], f[l], ns(l, 0), rl, pre);
     if (rc) return rc;
     rc = k_apply<T>(h, l, 1, u[l], f[l], rl, nullptr, nullptr);
     if (rc) return rc;

@@ -64,10 +64,10 @@ int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, 
 
 template <class T, int DIM>
 int Kern<T, DIM>::combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
-                          int npy, int npz, hipStream_t s) {
+                          int npy, int npz, bool assign, hipStream_t s) {
   switch (L.NP) {
 #define DGMG_CASE(NP) \
-  case NP: return combine_launch_t<T, DIM, NP>(L, nd, NA, NL, buf, u, npx, npy, npz, s);
+  case NP: return combine_launch_t<T, DIM, NP>(L, nd, NA, NL, buf, u, npx, npy, npz, assign, s);
     DGMG_NP_LIST(DGMG_CASE)
 #undef DGMG_CASE
     default: return -4;

@@ -913,7 +913,8 @@ int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int 
 }
 
 // ================================================================ overlap summation
-// u += sum_s R_s^T (w_s Delta u_s), gathered per node in a fixed order over the
+// u += sum_s R_s^T (w_s Delta u_s) (assign: u = the sum, for u = 0 on entry),
+// gathered per node in a fixed order over the
 // (at most 2 x 3 x 3) covering patches: deterministic, no atomics.  One block
 // per group of elements; per element and direction the candidate patches of
 // each local index are tabulated in LDS as address components, so a node's sum
@@ -926,7 +927,7 @@ constexpr int combine_epb() {
 template <class T, int DIM, int NP, int MAXC>
 __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
                                                       const T* __restrict__ buf, T* __restrict__ u,
-                                                      int npx, int npy, int npz, int nblk) {
+                                                      int npx, int npy, int npz, int nblk, bool assign) {
   constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>();
   constexpr int P = NP - 1;
   constexpr int CZ = DIM == 3 ? MAXC : 1;
@@ -995,22 +996,25 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
 #pragma unroll
         for (int a = 0; a < MAXC; ++a)
           s += T(c < nz && b < ny && a < nx ? 1 : 0) * v[c][b][a];  // s + 0 v = s: order unchanged
-    u[g0 + q] += s;
+    if (assign)
+      u[g0 + q] = s;
+    else
+      u[g0 + q] += s;
   }
 }
 
 template <class T, int DIM, int NP>
 int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
-                     int npy, int npz, hipStream_t s) {
+                     int npy, int npz, bool assign, hipStream_t s) {
   constexpr int EPB = combine_epb<NP, DIM>();
   const int nblk = (L.n_elem + EPB - 1) / EPB;
   // three covering element-centred patches in one direction only when 2 N_O > N_P
   if (2 * L.NO > NP)
     hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
-                       NL, buf, u, npx, npy, npz, nblk);
+                       NL, buf, u, npx, npy, npz, nblk, assign);
   else
     hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 2>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
-                       NL, buf, u, npx, npy, npz, nblk);
+                       NL, buf, u, npx, npy, npz, nblk, assign);
   return 0;
 }
 
@@ -1098,8 +1102,9 @@ struct Kern {
   static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
                  int npz, int waves, hipStream_t s);
   static bool fdm_supported(int NA, int NL);
+  // assign: u = the overlap sum (u is zero on entry) instead of u += it
   static int combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
-                     int npy, int npz, hipStream_t s);
+                     int npy, int npz, bool assign, hipStream_t s);
   // tmp: scratch of transfer_big_scratch(n_elem, NP, NPc) elements (3D levels with NP = 33 only)
   static int transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, T* tmp, hipStream_t s);
 };
