@@ -1027,56 +1027,72 @@ constexpr int xfer_epb() {
   return imax(1, 512 / ipow(NPF, DIM));
 }
 
+// One contraction pass of the transfer along direction D, all extents known at
+// compile time: before the pass directions < D have NOUT points and the others
+// NIN; the pass maps direction D from NIN to NOUT points.
+template <class T, int DIM, int NIN, int NOUT, int NEF, int D, bool RESTRICT, int NPC>
+__device__ __forceinline__ void xfer_pass(const T* __restrict__ sJ, const T* __restrict__ src,
+                                          T* __restrict__ dst, int ne) {
+  constexpr int n0 = D > 0 ? NOUT : NIN, n1 = D > 1 ? NOUT : NIN;
+  constexpr int m0 = NOUT * (D == 0) + n0 * (D != 0);
+  constexpr int m1 = DIM >= 2 ? (D >= 1 ? NOUT : NIN) : 1;
+  constexpr int m2 = DIM == 3 ? (D == 2 ? NOUT : NIN) : 1;
+  constexpr int per = m0 * m1 * m2;
+  constexpr int SK = D == 0 ? 1 : (D == 1 ? n0 : n0 * n1);  // source stride of direction D
+  for (int q = threadIdx.x; q < ne * per; q += blockDim.x) {
+    const int el = q / per, r = q - el * per;
+    const int i0 = r % m0, i1 = (r / m0) % m1, i2 = r / (m0 * m1);
+    const int iout = D == 0 ? i0 : (D == 1 ? i1 : i2);
+    // source position with the direction-D index set to 0
+    const int j0 = D == 0 ? 0 : i0, j1 = D == 1 ? 0 : i1, j2 = D == 2 ? 0 : i2;
+    const T* sp = src + el * NEF + (j2 * n1 + j1) * n0 + j0;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const T jv = RESTRICT ? sJ[k * NPC + iout] : sJ[iout * NPC + k];
+      s += jv * sp[k * SK];
+    }
+    dst[el * NEF + r] = s;
+  }
+}
+
 template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
 __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, int n_elem,
                                                        const T* __restrict__ in, T* __restrict__ out,
                                                        const int* __restrict__ active) {
   if (inactive(active)) return;
-  constexpr int NEF = ipow(NPF, DIM), NEC = ipow(NPC, DIM), EPB = xfer_epb<NPF, DIM>();
+  constexpr int NEF = ipow(NPF, DIM), EPB = xfer_epb<NPF, DIM>();
   constexpr int NIN = RESTRICT ? NPF : NPC, NOUT = RESTRICT ? NPC : NPF;
   constexpr int NEI = ipow(NIN, DIM), NEO = ipow(NOUT, DIM);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufB = bufA + EPB * NEF;
+  __shared__ T sJ[NPF * NPC];
   const int e0 = blockIdx.x * EPB;
   const int ne = imin(EPB, n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = J[q];
   for (int q = tid; q < ne * NEI; q += nth) {
     const int el = q / NEI, r = q - el * NEI;
     bufA[el * NEF + r] = in[(int64_t)e0 * NEI + q];  // per-element stride NEF in LDS
   }
   __syncthreads();
-  // pass over each direction: dims before the pass (out size for done dirs)
-  T* src = bufA;
-  T* dst = bufB;
-  int n0 = NIN, n1 = NIN, n2 = DIM == 3 ? NIN : 1;  // current extents (x fastest)
-#pragma unroll 1
-  for (int d = 0; d < DIM; ++d) {
-    int m0 = n0, m1 = n1, m2 = n2;
-    if (d == 0) m0 = NOUT; else if (d == 1) m1 = NOUT; else m2 = NOUT;
-    const int per = m0 * m1 * m2;
-    for (int q = tid; q < ne * per; q += nth) {
-      const int el = q / per, r = q - el * per;
-      const int i0 = r % m0, i1 = (r / m0) % m1, i2 = r / (m0 * m1);
-      const int iout = d == 0 ? i0 : (d == 1 ? i1 : i2);
-      T s = 0;
-      for (int k = 0; k < NIN; ++k) {
-        const int j0 = d == 0 ? k : i0, j1 = d == 1 ? k : i1, j2 = d == 2 ? k : i2;
-        const T jv = RESTRICT ? J[k * NPC + iout] : J[iout * NPC + k];
-        s += jv * src[el * NEF + (j2 * n1 + j1) * n0 + j0];
-      }
-      dst[el * NEF + r] = s;
-    }
+  xfer_pass<T, DIM, NIN, NOUT, NEF, 0, RESTRICT, NPC>(sJ, bufA, bufB, ne);
+  __syncthreads();
+  xfer_pass<T, DIM, NIN, NOUT, NEF, 1, RESTRICT, NPC>(sJ, bufB, bufA, ne);
+  __syncthreads();
+  const T* res = bufA;
+  if constexpr (DIM == 3) {
+    xfer_pass<T, DIM, NIN, NOUT, NEF, 2, RESTRICT, NPC>(sJ, bufA, bufB, ne);
     __syncthreads();
-    n0 = m0; n1 = m1; n2 = m2;
-    T* tmp = src; src = dst; dst = tmp;
+    res = bufB;
   }
   for (int q = tid; q < ne * NEO; q += nth) {
     const int el = q / NEO, r = q - el * NEO;
     if (RESTRICT)
-      out[(int64_t)e0 * NEO + q] = src[el * NEF + r];
+      out[(int64_t)e0 * NEO + q] = res[el * NEF + r];
     else
-      out[(int64_t)e0 * NEO + q] += src[el * NEF + r];
+      out[(int64_t)e0 * NEO + q] += res[el * NEF + r];
   }
 }
 
