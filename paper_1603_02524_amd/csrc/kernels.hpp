@@ -409,6 +409,11 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
 #ifndef DGMG_FDM_GATHER2D
 #define DGMG_FDM_GATHER2D 1
 #endif
+// Matrix operands of consecutive passes in two register sets used in turn
+// (the next pass's matrix loads while the current pass runs).
+#ifndef DGMG_FDM_PING
+#define DGMG_FDM_PING 1
+#endif
 
 // v / d for d > 0 of moderate magnitude (sums of patch eigenvalues): hardware
 // reciprocal estimate, Newton-Raphson refinement of 1/d, then one residual
@@ -503,6 +508,20 @@ template <class T, int LEN>
 struct BOp {
   static constexpr int KS = (LEN + 3) / 4, NB = (LEN + 15) / 16;
   T b[NB][KS];
+  // the matrix of another length with the same register shape (KS, NB)
+  template <int LEN2>
+  __device__ __forceinline__ void load_as(const T* __restrict__ Bm) {
+    static_assert((LEN2 + 3) / 4 == KS && (LEN2 + 15) / 16 == NB, "register shapes differ");
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lk, j = nb * 16 + li;
+        const T v = Bm[imin(k, LEN2 - 1) * LEN2 + imin(j, LEN2 - 1)];
+        b[nb][ks] = (k < LEN2 && j < LEN2) ? v : T(0);
+      }
+  }
   __device__ __forceinline__ void load(const T* __restrict__ Bm) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -534,9 +553,12 @@ struct NoPost {
 // results of lines past the set are discarded), and stores of rows j >= LEN or
 // of lines past the set go to the lane's slot of `trash` (64 values, dead
 // storage) instead of being masked.
-template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost, int BLEN = (TD == 0 ? NA : NL)>
 __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ trash,
-                                         const BOp<T, TD == 0 ? NA : NL>& B, Post post = Post()) {
+                                         const BOp<T, BLEN>& B, Post post = Post()) {
+  static_assert(BOp<T, BLEN>::KS == BOp<T, TD == 0 ? NA : NL>::KS &&
+                    BOp<T, BLEN>::NB == BOp<T, TD == 0 ? NA : NL>::NB,
+                "operand register shape");
   // Product D = B^T V^T: the A operand is B^T (held as B.b), the B operand the
   // lines; lane (li, lk) then owns output column li = its own line, rows
   // j = 16 nb + row(lk, r), so results go back along the line it loaded.
@@ -774,6 +796,13 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   constexpr bool PRE = DGMG_FDM_PRELOAD && NA <= 16 && NL <= 16;
   BOp<T, NA> F0, B0;
   BOp<T, NL> F1, B1, F2, B2;
+  // two operand register sets used in turn (3D, every pass on the matrix cores,
+  // both lengths with the same register shape)
+  constexpr bool PING = DGMG_FDM_PING && !PRE && DIM == 3 && NA > DGMG_FDM_VALU_MAXLEN &&
+                        NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
+                        BOp<T, NA>::NB == BOp<T, NL>::NB;
+  BOp<T, NA> P, Q;
+  if constexpr (PING) P.load(fwd[0]);
   if constexpr (PRE) {
     F0.load(fwd[0]);
     F1.load(fwd[1]);
@@ -844,6 +873,27 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     if constexpr (DGMG_FDM_DIV_NR) return div_nr(v, den);
     else return v / den;
   };
+  if constexpr (PING) {
+    // every pass on the matrix cores with one register shape: the next pass's
+    // matrix is loaded into the idle set while the current pass runs
+    Q.template load_as<NL>(fwd[1]);
+    fdm_pass<T, NA, NL, DIM, 0, NoPost, NA>(tile, trash, P);
+    __syncthreads();
+    P.template load_as<NL>(fwd[2]);
+    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA>(tile, trash, Q);
+    __syncthreads();
+    Q.template load_as<NL>(bwd[2]);
+    fdm_pass<T, NA, NL, DIM, 2, decltype(scale), NA>(tile, trash, P, scale);
+    __syncthreads();
+    P.template load_as<NL>(bwd[1]);
+    fdm_pass<T, NA, NL, DIM, 2, NoPost, NA>(tile, trash, Q);
+    __syncthreads();
+    Q.template load_as<NA>(bwd[0]);
+    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA>(tile, trash, P);
+    __syncthreads();
+    fdm_pass<T, NA, NL, DIM, 0, NoPost, NA>(tile, trash, Q);
+    __syncthreads();
+  } else {
   if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, fwd[0], bwd[0]);
   __syncthreads();
   if constexpr (DIM == 3) {
@@ -864,6 +914,7 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
   __syncthreads();
   if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, bwd[0], fwd[0]);
   __syncthreads();
+  }
   // weighted result w_s (.) Delta u_s in grid-natural order
   T* dst = out + (int64_t)pid * TS;
   if constexpr (G2D) {
