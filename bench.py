@@ -45,7 +45,7 @@ HBM_PEAK_GBPS = 8000.0
 # the patch-solve section of kernels.hpp is compared at run time and the
 # figure dropped on any change.
 TRAFFIC = {"bytes_per_launch": 133.7e6,
-           "kernel_src_sha256": "68859f5ff6adf6f1b7663ddcba25d0583f96dbcddf7091901d5f824d6de2e643",
+           "kernel_src_sha256": "d3fd0d784b60587f2a997e298f58a0357bd97c371441c5d0bf8f21f33a6b784d",
            "profile": "profiles/fdm_p8_c2_fp64_pmc_traffic.md"}
 KERNEL_SOURCE = "paper_1603_02524_amd/csrc/kernels.hpp"
 KERNEL_SECTION = ("// ================================================================ FDM patch solve",
