@@ -974,20 +974,31 @@ template <int NP, int DIM>
 constexpr int combine_epb() {
   return imax(1, 256 / ipow(NP, DIM));
 }
+// Large elements are split over several blocks of at most COMBINE_CHUNK nodes
+// (a whole P = 32 element per block left 512 blocks, each thread looping 140
+// times through latency-bound candidate loads).
+constexpr int COMBINE_CHUNK = 2048;
+template <int NP, int DIM>
+constexpr int combine_bpe() {
+  return combine_epb<NP, DIM>() == 1 ? (ipow(NP, DIM) + COMBINE_CHUNK - 1) / COMBINE_CHUNK : 1;
+}
 
 template <class T, int DIM, int NP, int MAXC>
 __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
                                                       const T* __restrict__ buf, T* __restrict__ u,
                                                       int npx, int npy, int npz, int nblk, bool assign) {
-  constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>();
+  constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>(), BPE = combine_bpe<NP, DIM>();
   constexpr int P = NP - 1;
   constexpr int CZ = DIM == 3 ? MAXC : 1;
   __shared__ int64_t cadr[EPB][3][NP][MAXC];
   __shared__ int ccnt[EPB][3][NP];
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
-  const int e0 = blk * EPB;
-  const int ne = imin(EPB, L.n_elem - e0);
+  // BPE > 1: block blk takes nodes [q_lo, q_hi) of element blk / BPE
+  const int e0 = BPE > 1 ? blk / BPE : blk * EPB;
+  const int ne = BPE > 1 ? 1 : imin(EPB, L.n_elem - e0);
+  const int q_lo = BPE > 1 ? (blk % BPE) * COMBINE_CHUNK : 0;
+  const int q_hi = BPE > 1 ? imin(NE, q_lo + COMBINE_CHUNK) : ne * NE;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int N1 = L.dir[0].N, N2 = L.dir[1].N, NO = L.NO;
   int len[3] = {1, 1, 1};
@@ -1023,7 +1034,7 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
   // each node: all its (at most MAXC per direction) candidates are loaded before
   // the sum, then added in a fixed order (z, y, x candidates)
   const int64_t g0 = (int64_t)e0 * NE;
-  for (int q = tid; q < ne * NE; q += nth) {
+  for (int q = q_lo + tid; q < q_hi; q += nth) {
     const int el = q / NE, loc = q - el * NE;
     const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
     const int nx = ccnt[el][0][i], ny = ccnt[el][1][j], nz = ccnt[el][2][k];
@@ -1057,8 +1068,8 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
 template <class T, int DIM, int NP>
 int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, bool assign, hipStream_t s) {
-  constexpr int EPB = combine_epb<NP, DIM>();
-  const int nblk = (L.n_elem + EPB - 1) / EPB;
+  constexpr int EPB = combine_epb<NP, DIM>(), BPE = combine_bpe<NP, DIM>();
+  const int nblk = BPE > 1 ? L.n_elem * BPE : (L.n_elem + EPB - 1) / EPB;
   // three covering element-centred patches in one direction only when 2 N_O > N_P
   if (2 * L.NO > NP)
     hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,

@@ -222,21 +222,40 @@ int apply_big_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* 
 // directions per (element, k') plane in LDS.  Prolongation out_f += (J x J x J)
 // in_c: the two fast directions per coarse plane into tmp [e][k][j][i], then
 // the slowest direction accumulated into out.
+// One thread per (element, fine column ji): the column's NPF values are read
+// once and give all NPC outputs; the rows of J are uniform, read by scalar
+// loads (each output still sums k = 0, 1, ... in order).
 template <class T, int NPF, int NPC>
 __global__ void __launch_bounds__(256) restrict_z_kernel(const T* __restrict__ J, int n_elem,
                                                          const T* __restrict__ in, T* __restrict__ tmp,
                                                          const int* __restrict__ active) {
   if (inactive(active)) return;
   constexpr int PL = NPF * NPF, NEF = NPF * PL, PER = NPC * PL;
-  const int64_t total = (int64_t)n_elem * PER;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = q / PER;
-    const int r = (int)(q - e * PER), kc = r / PL, ji = r - kc * PL;
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Jc = (CT*)J;
+  const int64_t total = (int64_t)n_elem * PL;
+  // one column per thread (no grid-stride loop: J's rows would be hoisted out of it)
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < total) {
+    const int64_t e = q / PL;
+    const int ji = (int)(q - e * PL);
     const T* src = in + e * NEF + ji;
-    T s = 0;
+    T v[NPF];
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) s += J[k * NPC + kc] * src[k * PL];
-    tmp[q] = s;
+    for (int k = 0; k < NPF; ++k) v[k] = src[k * PL];
+    T acc[NPC];
+#pragma unroll
+    for (int kc = 0; kc < NPC; ++kc) acc[kc] = T(0);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+#pragma unroll
+      for (int kc = 0; kc < NPC; ++kc) acc[kc] += Jc[k * NPC + kc] * v[k];
+      // two rows of J in scalar registers at a time (no hoisting of all of J)
+      if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    T* dst = tmp + e * PER + ji;
+#pragma unroll
+    for (int kc = 0; kc < NPC; ++kc) dst[kc * PL] = acc[kc];
   }
 }
 
@@ -304,21 +323,36 @@ __global__ void __launch_bounds__(256) prolong_xy_kernel(const T* __restrict__ J
   }
 }
 
+// One thread per (element, column ji): the NPC coarse values of the column are
+// read once and update all NPF fine values (each sums kc = 0, 1, ... in order).
 template <class T, int NPF, int NPC>
 __global__ void __launch_bounds__(256) prolong_z_kernel(const T* __restrict__ J, int n_elem,
                                                         const T* __restrict__ tmp, T* __restrict__ out,
                                                         const int* __restrict__ active) {
   if (inactive(active)) return;
   constexpr int PL = NPF * NPF, NEF = NPF * PL, TPE = NPC * PL;
-  const int64_t total = (int64_t)n_elem * NEF;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = q / NEF;
-    const int r = (int)(q - e * NEF), k = r / PL, ji = r - k * PL;
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Jc = (CT*)J;
+  const int64_t total = (int64_t)n_elem * PL;
+  // one column per thread (no grid-stride loop: J's rows would be hoisted out of it)
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < total) {
+    const int64_t e = q / PL;
+    const int ji = (int)(q - e * PL);
     const T* src = tmp + e * TPE + ji;
-    T s = 0;
+    T w[NPC];
 #pragma unroll
-    for (int kc = 0; kc < NPC; ++kc) s += J[k * NPC + kc] * src[kc * PL];
-    out[q] += s;
+    for (int kc = 0; kc < NPC; ++kc) w[kc] = src[kc * PL];
+    T* dst = out + e * NEF + ji;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      T s = 0;
+#pragma unroll
+      for (int kc = 0; kc < NPC; ++kc) s += Jc[k * NPC + kc] * w[kc];
+      dst[k * PL] += s;
+      // two rows of J in scalar registers at a time (no hoisting of all of J)
+      if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -328,17 +362,16 @@ inline int64_t transfer_big_scratch(int n_elem, int NPF, int NPC) { return (int6
 template <class T, int NPF, int NPC>
 int transfer_big_launch(const T* J, int n_elem, bool restrict_, const T* in, T* out, T* tmp, const int* active,
                         hipStream_t s) {
-  const int64_t nz = (int64_t)n_elem * NPC * NPF * NPF;
-  const unsigned gz = (unsigned)imin(65536, (int)((nz + 255) / 256));
+  // z stages: one thread per (element, column)
+  const int64_t ncol = (int64_t)n_elem * NPF * NPF;  // < 2^31 / NPF columns
+  const unsigned gz = (unsigned)((ncol + 255) / 256);
   const unsigned gp = (unsigned)(n_elem * NPC);
   if (restrict_) {
     hipLaunchKernelGGL((restrict_z_kernel<T, NPF, NPC>), dim3(gz), dim3(256), 0, s, J, n_elem, in, tmp, active);
     hipLaunchKernelGGL((restrict_xy_kernel<T, NPF, NPC>), dim3(gp), dim3(256), 0, s, J, n_elem, tmp, out, active);
   } else {
-    const int64_t nf = (int64_t)n_elem * NPF * NPF * NPF;
-    const unsigned gf = (unsigned)imin(65536, (int)((nf + 255) / 256));
     hipLaunchKernelGGL((prolong_xy_kernel<T, NPF, NPC>), dim3(gp), dim3(256), 0, s, J, n_elem, in, tmp, active);
-    hipLaunchKernelGGL((prolong_z_kernel<T, NPF, NPC>), dim3(gf), dim3(256), 0, s, J, n_elem, tmp, out, active);
+    hipLaunchKernelGGL((prolong_z_kernel<T, NPF, NPC>), dim3(gz), dim3(256), 0, s, J, n_elem, tmp, out, active);
   }
   return 0;
 }
