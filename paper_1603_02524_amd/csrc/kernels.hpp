@@ -176,7 +176,15 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   const int64_t g0 = (int64_t)e0 * NE;
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   // stiffness matrix rows: uniform addresses in the constant address space,
-  // so the row loop reads them with scalar loads into SGPR operands
+  // so the row loop reads them with scalar loads into SGPR operands; rows
+  // longer than 72 bytes (2D, large P) would not fit the scalar registers and
+  // are staged in LDS instead (uniform-address reads)
+  constexpr bool SLS = NP * sizeof(T) <= 72;
+  __shared__ T sLsL[SLS ? 1 : NP * NP];
+  if constexpr (!SLS) {
+    for (int q = tid; q < NP * NP; q += nth) sLsL[q] = L.Ls[q];
+    __syncthreads();
+  }
   using CT = const __attribute__((address_space(4))) T;
   CT* __restrict__ Ls = (CT*)L.Ls;
   CT* __restrict__ D0 = (CT*)L.D;
@@ -305,7 +313,10 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
     for (int i = 0; i < NP; ++i) {
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) s += Ls[__builtin_amdgcn_readfirstlane(i) * NP + k] * v[k];
+      for (int k = 0; k < NP; ++k) {
+        if constexpr (SLS) s += Ls[__builtin_amdgcn_readfirstlane(i) * NP + k] * v[k];
+        else s += sLsL[i * NP + k] * v[k];
+      }
       const int iu = __builtin_amdgcn_readfirstlane(i);
       T o = tdx * s + cl * D0[iu] - cr * DP[iu];
       if (i == 0) o += fl;

@@ -75,17 +75,18 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
   constexpr int CH = (NLN + LB - 1) / LB;  // line chunks per element
   constexpr int SX = D == 0 ? LB * NP : 1;
   __shared__ double red[16];
-  __shared__ T sLs[NP * NP], sD0[NP], sDP[NP], srho[NP];
+  __shared__ T srho[NP];
   __shared__ T sx[SX];
   const int b = xcd_block(nblk);
   if (b < 0 || inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
-  for (int q = tid; q < NP; q += nth) {
-    sD0[q] = L.D[q];
-    sDP[q] = L.D[P * NP + q];
-    srho[q] = L.rho[q];
-  }
+  for (int q = tid; q < NP; q += nth) srho[q] = L.rho[q];
+  // the stiffness matrix and end-derivative rows: uniform addresses in the
+  // constant address space, read with scalar loads into SGPR operands
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ sLs = (CT*)L.Ls;
+  CT* __restrict__ sD0 = (CT*)L.D;
+  CT* __restrict__ sDP = (CT*)(L.D + P * NP);
   const int e = b / CH, c0 = (b - e * CH) * LB, t = c0 + tid;
   const int nlines = imin(LB, NLN - c0);
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
@@ -151,10 +152,11 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
     const T mo = ha * srho[ia] * hb * srho[ib];
 #pragma unroll 1
     for (int i = 0; i < NP; ++i) {
+      const int iu = __builtin_amdgcn_readfirstlane(i);
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) s += sLs[i * NP + k] * v[k];
-      T o = tdx * s + cl * sD0[i] - cr * sDP[i];
+      for (int k = 0; k < NP; ++k) s += sLs[iu * NP + k] * v[k];
+      T o = tdx * s + cl * sD0[iu] - cr * sDP[iu];
       if (i == 0) o += fl;
       if (i == P) o += fr;
       const T val = mo * o;
@@ -167,7 +169,9 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
         } else {
           const T tot = y[idx] + val;
           y[idx] = tot;
-          if (MODE == 2 && D == 2) acc += (double)v[i] * (double)tot;
+          // v_i read again from x: indexing v by the rolled loop counter
+          // would put the line in scratch memory
+          if (MODE == 2 && D == 2) acc += (double)x[g0 + base + i * stride] * (double)tot;
         }
       }
     }
