@@ -540,7 +540,9 @@ __global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ 
   for (int e = tid; e < N0 * N2; e += nth) {
     const int o2 = e / N0, o0 = e - o2 * N0;
     const int i = o2 * PT + o0;
-    pl[i] = pl[i] / (l0[o0] + l1 + l2[o2]);
+    const T den = l0[o0] + l1 + l2[o2];
+    if constexpr (DGMG_FDM_DIV_NR) pl[i] = div_nr(pl[i], den);  // Newton-refined reciprocal
+    else pl[i] = pl[i] / den;
   }
   __syncthreads();
   mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.ST[2]);
