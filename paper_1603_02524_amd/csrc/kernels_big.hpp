@@ -592,7 +592,10 @@ void fdm_big_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int np
   const int npatch = npx * npy * npz;
   hipLaunchKernelGGL((fdm_big_a<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, r, out, npx,
                      npy, npz);
-  hipLaunchKernelGGL((fdm_big_b<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L1)), dim3(256), 0, s, L, out, npx,
+  // stage B contracts only along direction 2: one wave per output column block
+  // (3 for length 43: a fourth wave would idle through both passes)
+  constexpr int thb = 64 * ((Q::L2 + 15) / 16);
+  hipLaunchKernelGGL((fdm_big_b<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L1)), dim3(thb), 0, s, L, out, npx,
                      npy, npz);
   hipLaunchKernelGGL((fdm_big_c<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, out, npx,
                      npy, npz);
