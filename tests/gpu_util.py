@@ -32,6 +32,9 @@ CASES = [
     ("3d_dir_ip_p12_fa", dict(dim=3, n=(2, 2, 1), seed=9), dict(P=12, smoother="FA")),
     ("3d_dir_ip_p16_ea", dict(dim=3, n=(2, 1, 2), seed=10), dict(P=16, smoother="EA")),
     ("3d_dir_ip_p16_fa", dict(dim=3, n=(1, 2, 2), seed=13), dict(P=16, smoother="FA")),
+    # 2D at high order: long rows of the element apply and the patch solves in 2D tiles
+    ("2d_dir_ip_p16_fa", dict(dim=2, n=(3, 2), seed=14), dict(P=16, smoother="FA")),
+    ("2d_per_ip_p32_ea", dict(dim=2, n=(3, 3), periodic=True, seed=15), dict(P=32, smoother="EA")),
     # P = 32: 3D elements and patch tiles beyond LDS (two-stage transfers, three-stage patch solves)
     ("3d_dir_ip_p32_fa", dict(dim=3, n=(2, 1, 2), seed=11), dict(P=32, smoother="FA")),
     ("3d_dir_ip_p32_ea", dict(dim=3, n=(1, 2, 2), seed=12), dict(P=32, smoother="EA")),

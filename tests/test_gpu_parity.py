@@ -188,7 +188,8 @@ def test_solve_is_deterministic(pair):
     assert torch.equal(x1, x2)
 
 
-@pytest.mark.parametrize("cid", ["3d_dir_ldg_p4_ea", "3d_dir_ip_p8_fa", "2d_per_ldg_p3_fa", "3d_dir_ip_p32_fa"])
+@pytest.mark.parametrize("cid", ["3d_dir_ldg_p4_ea", "3d_dir_ip_p8_fa", "2d_per_ldg_p3_fa", "3d_dir_ip_p32_fa",
+                                 "2d_per_ip_p32_ea"])
 def test_mixed_precision_solve(cid):
     """FP32 V-cycle inside FP64 PCG reaches the same 1e-10 true residual."""
     from oracle import multigrid as mg
