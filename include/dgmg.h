@@ -199,8 +199,12 @@ int dgmg_vcycle(dgmg_handle* h, const void* r, void* z, int dtype);
  * device vectors of the top level; x holds the initial guess on entry and the
  * iterate on exit.  Synchronises the stream once per iteration (exit test).
  * st (host, may be NULL) receives iteration count and residual history.
- * Returns DGMG_OK, DGMG_NOT_CONVERGED or an error (DGMG_ENONFINITE when a
- * residual norm is NaN/Inf). */
+ * On a grid periodic in every direction A is singular (constants span its
+ * null space) and rhs must sum to zero, |sum rhs| <= 1e-10 sum |rhs|; the
+ * returned x is then determined up to a constant.
+ * Returns DGMG_OK, DGMG_NOT_CONVERGED or an error (DGMG_EINVAL for a fully
+ * periodic rhs that does not sum to zero, DGMG_ENONFINITE when a residual norm
+ * is NaN/Inf). */
 int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_stats* st);
 
 /* g = M f: the GLL load vector of Sec. 2.4 from nodal values f (FP64 device

@@ -54,6 +54,50 @@ __global__ void __launch_bounds__(VEC_THREADS) k_finalize(const double* __restri
   if (threadIdx.x == 0) out[0] = s;
 }
 
+// Phase-b scalars in one block: n = z.(r - r_old) and z.r from their partials
+// (each in a fixed order), then beta = n / delta with the previous delta, and
+// delta <- z.r.  scal slots: 0 delta, 1 beta, 4 n, 5 z.r.
+__global__ void __launch_bounds__(VEC_THREADS) k_finalize_beta(const double* __restrict__ part1,
+                                                               const double* __restrict__ part2, int np,
+                                                               double* __restrict__ scal, const int* act) {
+  if (inactive(act)) return;
+  __shared__ double red[16];
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    s1 += part1[i];
+    s2 += part2[i];
+  }
+  s1 = block_sum(s1, red);
+  __syncthreads();
+  s2 = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    scal[4] = s1;
+    scal[5] = s2;
+    scal[1] = s1 / scal[0];
+    scal[0] = s2;
+  }
+}
+
+// sum a_i and sum |a_i| partials.
+__global__ void __launch_bounds__(VEC_THREADS) k_sum_abs(const double* __restrict__ a, int64_t n,
+                                                         double* __restrict__ part1,
+                                                         double* __restrict__ part2, const int* act) {
+  if (inactive(act)) return;
+  __shared__ double red[16];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    s1 += a[i];
+    s2 += fabs(a[i]);
+  }
+  s1 = block_sum(s1, red);
+  __syncthreads();
+  s2 = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    part1[blockIdx.x] = s1;
+    part2[blockIdx.x] = s2;
+  }
+}
+
 // z.(r - r_old) and z.r partials.
 __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const double* __restrict__ z,
                                                         const double* __restrict__ r,
@@ -98,15 +142,14 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// beta = num / delta_old; p = z + beta p; r_old = r
+// p = z + beta p; r_old = r
 __global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p, const double* __restrict__ z,
                                                           const double* __restrict__ r,
                                                           double* __restrict__ ro,
-                                                          const double* __restrict__ num,
-                                                          const double* __restrict__ delta_old,
+                                                          const double* __restrict__ beta_p,
                                                           int64_t n, const int* act) {
   if (inactive(act)) return;
-  const double beta = num[0] / delta_old[0];
+  const double beta = beta_p[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     p[i] = z[i] + beta * p[i];
     ro[i] = r[i];
@@ -262,7 +305,7 @@ struct dgmg_handle {
   // PCG (top level, FP64)
   double *pr = nullptr, *pro = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;
   double *part = nullptr, *part2 = nullptr;  // reduction partials
-  double* scal = nullptr;                    // slots: 0 delta, 2 p.q, 3 r.r, 4 z.(r-r_old), 5 z.r
+  double* scal = nullptr;                    // slots: 0 delta, 1 beta, 2 p.q, 3 r.r, 4 z.(r-r_old), 5 z.r
   double* host_scal = nullptr;               // pinned
   // batched use: device flag (kernels return when 0) and the slot receiving r.r
   const int* active = nullptr;
@@ -740,7 +783,7 @@ int precond(dgmg_handle* h, const double* r, double* z) {
 
 // ---------------------------------------------------------------- MGCG phases (Alg. 2)
 // Fixed device scalar slots so that a phase can be captured once and replayed.
-enum { S_DELTA = 0, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5 };
+enum { S_DELTA = 0, S_BETA = 1, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5 };
 
 double* rr_slot(dgmg_handle* h) { return h->rr_out ? h->rr_out : h->scal + S_RR; }
 
@@ -789,11 +832,10 @@ int pcg_phase_b(dgmg_handle* h) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_dot_zr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro, n,
                      h->part, h->part2, h->active);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + S_ZDR, h->active);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, h->scal + S_ZR, h->active);
+  hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, h->part2, RED_BLOCKS,
+                     h->scal, h->active);
   hipLaunchKernelGGL(k_update_p, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, h->pz, h->pr, h->pro,
-                     h->scal + S_ZDR, h->scal + S_DELTA, n, h->active);
-  hipLaunchKernelGGL(k_copy, dim3(1), dim3(64), 0, h->stream, h->scal + S_ZR, h->scal + S_DELTA, (int64_t)1, h->active);
+                     h->scal + S_BETA, n, h->active);
   return check_hip(h, "pcg phase b");
 }
 
@@ -1182,6 +1224,21 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
   if (!rhs || !x || !(tol >= 0)) return fail(h, DGMG_EINVAL, "bad arguments");
   if (h->active) return fail(h, DGMG_EINVAL, "handle belongs to a batch");
   if (st) std::memset(st, 0, sizeof(*st));
+  const LevelHost& top = h->lv.back();
+  bool periodic_all = true;
+  for (int d = 0; d < top.dim; ++d) periodic_all = periodic_all && top.dir[d].periodic;
+  if (periodic_all) {
+    // A is singular (the constants span its null space): the system is
+    // consistent only for a right-hand side orthogonal to them
+    hipLaunchKernelGGL(k_sum_abs, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, rhs, top.n_dof, h->part,
+                       h->part2, h->active);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 42, h->active);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, h->scal + 43, h->active);
+    double sum, asum;
+    if ((rc = read_scalar(h, h->scal + 42, &sum)) || (rc = read_scalar(h, h->scal + 43, &asum))) return rc;
+    if (!(std::fabs(sum) <= 1e-10 * asum))
+      return fail(h, DGMG_EINVAL, "fully periodic grid: the right-hand side must sum to zero");
+  }
   if ((rc = pcg_init_a(h, rhs, x))) return rc;
   double rr;
   if ((rc = read_scalar(h, rr_slot(h), &rr))) return rc;

@@ -13,7 +13,8 @@ def rand_grid(dim, n, periodic=False, seed=0, lo=0.4, hi=1.6):
     if isinstance(n, int):
         n = (n,) * dim
     dx = tuple(rng.uniform(lo, hi, size=n[d]) for d in range(dim))
-    return synth.Grid(dim, dx, (periodic,) * dim)
+    per = tuple(periodic) if isinstance(periodic, (tuple, list)) else (periodic,) * dim
+    return synth.Grid(dim, dx, per)
 
 
 # (id, grid kwargs, method kwargs) -- element counts chosen so that blocks end ragged
@@ -35,6 +36,14 @@ CASES = [
     # 2D at high order: long rows of the element apply and the patch solves in 2D tiles
     ("2d_dir_ip_p16_fa", dict(dim=2, n=(3, 2), seed=14), dict(P=16, smoother="FA")),
     ("2d_per_ip_p32_ea", dict(dim=2, n=(3, 3), periodic=True, seed=15), dict(P=32, smoother="EA")),
+    # degenerate shapes: a single level (P = 1: the V-cycle is the exact coarse
+    # solve), a single element, and mixed periodic / Dirichlet directions
+    ("3d_dir_ip_p1_ea", dict(dim=3, n=(3, 2, 2), seed=21), dict(P=1, smoother="EA")),
+    ("2d_per_ip_p1_fa", dict(dim=2, n=(3, 4), periodic=True, seed=22), dict(P=1, smoother="FA")),
+    ("3d_dir_ip_1x1x1_p4_fa", dict(dim=3, n=(1, 1, 1), seed=23), dict(P=4, smoother="FA")),
+    ("3d_mixed_ip_p4_fa", dict(dim=3, n=(3, 2, 3), periodic=(True, False, True), seed=26), dict(P=4, smoother="FA")),
+    ("3d_mixed_ldg_p6_ea", dict(dim=3, n=(2, 3, 2), periodic=(False, True, False), seed=27),
+     dict(P=6, smoother="EA", flux="ldg", beta=(0.5, 0.5, 0.5))),
     # P = 32: 3D elements and patch tiles beyond LDS (two-stage transfers, three-stage patch solves)
     ("3d_dir_ip_p32_fa", dict(dim=3, n=(2, 1, 2), seed=11), dict(P=32, smoother="FA")),
     ("3d_dir_ip_p32_ea", dict(dim=3, n=(1, 2, 2), seed=12), dict(P=32, smoother="EA")),
