@@ -269,7 +269,8 @@ int dgmg_batch_autotune(dgmg_batch* b);
 int dgmg_batch_use_graphs(dgmg_batch* b, int enable);
 /* Solve all grids to ||r_i|| <= tol ||r_i,0|| (each grid's own max_iter);
  * st: host array of count dgmg_stats (may be NULL).  DGMG_NOT_CONVERGED if
- * any grid stopped unconverged. */
+ * any grid stopped unconverged; DGMG_EINVAL if a fully periodic grid's part of
+ * rhs does not sum to zero (as for dgmg_solve). */
 int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dgmg_stats* st);
 const char* dgmg_batch_last_error(const dgmg_batch* b);
 void dgmg_batch_destroy(dgmg_batch* b);

@@ -1218,27 +1218,33 @@ int dgmg_mass(dgmg_handle* h, const double* f, double* g) {
   return check_hip(h, "mass");
 }
 
+// On a grid periodic in every direction A is singular (the constants span its
+// null space): the system is consistent only for a right-hand side orthogonal
+// to them.  Other grids pass at once.
+static int check_rhs_consistent(dgmg_handle* h, const double* rhs) {
+  const LevelHost& top = h->lv.back();
+  bool periodic_all = true;
+  for (int d = 0; d < top.dim; ++d) periodic_all = periodic_all && top.dir[d].periodic;
+  if (!periodic_all) return DGMG_OK;
+  hipLaunchKernelGGL(k_sum_abs, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, rhs, top.n_dof, h->part,
+                     h->part2, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 42, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, h->scal + 43, h->active);
+  double sum, asum;
+  int rc;
+  if ((rc = read_scalar(h, h->scal + 42, &sum)) || (rc = read_scalar(h, h->scal + 43, &asum))) return rc;
+  if (!(std::fabs(sum) <= 1e-10 * asum))
+    return fail(h, DGMG_EINVAL, "fully periodic grid: the right-hand side must sum to zero");
+  return DGMG_OK;
+}
+
 int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_stats* st) {
   int rc = need_bound(h);
   if (rc) return rc;
   if (!rhs || !x || !(tol >= 0)) return fail(h, DGMG_EINVAL, "bad arguments");
   if (h->active) return fail(h, DGMG_EINVAL, "handle belongs to a batch");
   if (st) std::memset(st, 0, sizeof(*st));
-  const LevelHost& top = h->lv.back();
-  bool periodic_all = true;
-  for (int d = 0; d < top.dim; ++d) periodic_all = periodic_all && top.dir[d].periodic;
-  if (periodic_all) {
-    // A is singular (the constants span its null space): the system is
-    // consistent only for a right-hand side orthogonal to them
-    hipLaunchKernelGGL(k_sum_abs, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, rhs, top.n_dof, h->part,
-                       h->part2, h->active);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + 42, h->active);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, h->scal + 43, h->active);
-    double sum, asum;
-    if ((rc = read_scalar(h, h->scal + 42, &sum)) || (rc = read_scalar(h, h->scal + 43, &asum))) return rc;
-    if (!(std::fabs(sum) <= 1e-10 * asum))
-      return fail(h, DGMG_EINVAL, "fully periodic grid: the right-hand side must sum to zero");
-  }
+  if ((rc = check_rhs_consistent(h, rhs))) return rc;
   if ((rc = pcg_init_a(h, rhs, x))) return rc;
   double rr;
   if ((rc = read_scalar(h, rr_slot(h), &rr))) return rc;
@@ -1784,6 +1790,9 @@ int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dg
   for (int i = 0; i < n; ++i) b->flags_host[i] = 1;
   int rc = batch_flags_upload(b);
   if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    if ((rc = check_rhs_consistent(b->h[i], rhs + b->dof_off[i])))
+      return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);
   for (int i = 0; i < n; ++i)
     if ((rc = pcg_init_a(b->h[i], rhs + b->dof_off[i], x + b->dof_off[i])))
       return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);

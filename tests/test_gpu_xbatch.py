@@ -111,6 +111,37 @@ def test_batch_matches_single_and_oracle(graphs):
     B.close()
 
 
+def test_batch_with_periodic_grids():
+    """Fully periodic and mixed-boundary grids in one batch: each solved as by a
+    single handle, bit for bit; a periodic part of rhs that does not sum to zero
+    is rejected."""
+    probs = [(rand_grid(3, (2, 2, 1), seed=41), synth.Method(P=4, smoother="FA")),
+             (rand_grid(3, (3, 3, 3), periodic=True, seed=42), synth.Method(P=4, smoother="FA")),
+             (rand_grid(3, (3, 2, 3), periodic=(True, False, True), seed=43), synth.Method(P=3, smoother="EA"))]
+    B = D.BatchSolver(probs)
+    try:
+        f_all = np.random.default_rng(5).uniform(-1, 1, B.n_dof)
+        sp = slice(B.offsets[1], B.offsets[2])
+        f_all[sp] += 0.5
+        with pytest.raises(D.DgmgError) as ei:
+            B.solve(_dev(f_all), _dev(np.zeros(B.n_dof)))
+        assert ei.value.code == -1
+        f_all[sp] -= f_all[sp].mean()
+        x_all = _dev(np.zeros(B.n_dof))
+        stats = B.solve(_dev(f_all), x_all)
+        xb = x_all.cpu().numpy()
+        for i, (g, m) in enumerate(probs):
+            sl = slice(B.offsets[i], B.offsets[i + 1])
+            S = D.Solver(g, m)
+            xs = _dev(np.zeros(sl.stop - sl.start))
+            st = S.solve(_dev(f_all[sl]), xs)
+            assert stats[i]["converged"] and st["iterations"] == stats[i]["iterations"], i
+            assert np.array_equal(xs.cpu().numpy(), xb[sl]), i
+            S.close()
+    finally:
+        B.close()
+
+
 def test_batch_mixed_autotuned_converges():
     probs = _small_batch("mixed")
     B = D.BatchSolver(probs)
