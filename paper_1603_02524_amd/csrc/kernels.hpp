@@ -134,9 +134,10 @@ __device__ __forceinline__ P* sgpr_ptr(P* p) {
 
 // Own elements staged in LDS (coalesced loads) when the tiles are small: the
 // lines of the block's own elements are then read from LDS and only the
-// neighbours' lines from global memory.  Lines along direction 1 are strided
-// in memory (a load touches one cache line per lane), so this removes the
-// costliest third of the line loads.
+// neighbours' lines from global memory.  A line along direction 0 is contiguous,
+// so the lanes of a wave (one line each) are NP values apart and a load touches
+// about one cache line per lane: staging removes the costliest third of the line
+// loads.
 template <int NP, int DIM>
 constexpr bool apply_stage_own() {
   return NP <= 9 && apply_epb<NP, DIM>() * DIM * ipow(NP, DIM - 1) <= 1024;

@@ -4,6 +4,9 @@ Usage:
   python -m paper_1603_02524_amd.rocprof_summary stats <run_kernel_stats.csv> [top]
   python -m paper_1603_02524_amd.rocprof_summary pmc <solve_counter_collection.csv> <copy_counter_collection.csv>
                                   <counter> <bytes moved per copy>
+  python -m paper_1603_02524_amd.rocprof_summary counters <counter_collection.csv> [<csv> ...] -- <kernel> [<kernel> ...]
+      (per kernel whose short name starts with one of the given prefixes: each counter's mean
+       per dispatch and, where SQ_WAVES was collected, per wave)
 """
 import collections
 import csv
@@ -59,8 +62,28 @@ def pmc(solve, copy, counter, copy_bytes):
         print(f"| `{name}` | {len(v)} | {avg:.0f} | {avg * 1024 * scale / 1e6:.1f} |")
 
 
+def counters(paths, kernels):
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            name = short(r["Kernel_Name"])
+            if any(name.startswith(k) for k in kernels):
+                per[name][r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    for name in sorted(per):
+        cs = per[name]
+        mean = {c: sum(d.values()) / len(d) for c, d in cs.items()}
+        waves = mean.get("SQ_WAVES")
+        print(f"\n`{name}`\n\n| counter | dispatches | mean per dispatch | per wave |\n|---|---|---|---|")
+        for c in sorted(mean):
+            pw = f"{mean[c] / waves:.1f}" if waves else "-"
+            print(f"| {c} | {len(cs[c])} | {mean[c]:.0f} | {pw} |")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 24)
+    elif sys.argv[1] == "counters":
+        cut = sys.argv.index("--")
+        counters(sys.argv[2:cut], sys.argv[cut + 1:])
     else:
         pmc(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]))
