@@ -472,6 +472,34 @@ struct BigPatch {
 
 constexpr int big_pitch(int n) { return n % 2 == 0 ? n + 1 : n; }
 
+// Threads of the stage launches (compile-time: the copies below unroll over them).
+constexpr int BIG_AC_THREADS = 256;
+template <int L2>
+constexpr int big_b_threads() {
+  return 64 * ((L2 + 15) / 16);  // one wave per output column block of direction 2
+}
+
+// Move N values with every load of a thread issued before any of its stores
+// (a plain strided loop waits for each load before the next one starts).  NT
+// is the block size; ld(e) reads element e (called with e < N only), st(e, v)
+// writes it.
+template <class T, int NT, int N, class Ld, class St>
+__device__ __forceinline__ void big_copy(Ld ld, St st) {
+  constexpr int C = (N + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    v[c] = ld(e < N ? e : N - 1);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    if (e < N) st(e, v[c]);
+  }
+}
+
 // Stage A: block per (patch, o2).  Gather the plane o2 of R_s r, forward
 // transform along directions 0 and 1, store it in the patch's slot
 // (grid-natural order (o2 L1 + o1) L0 + o0).
@@ -492,23 +520,25 @@ __global__ void __launch_bounds__(256) fdm_big_a(LevelDev<T> L, const T* __restr
   for (int o = tid; o < N1; o += nth) g1[o] = q.go[1][o];
   const int gz = q.go[2][o2];
   __syncthreads();
-  for (int e = tid; e < N0 * N1; e += nth) {
+  // positions outside a Dirichlet domain read r[0] and store 0
+  const auto gidx = [&](int e) {
     const int o1 = e / N0, o0 = e - o1 * N0;
     const int a = g0[o0], b = g1[o1];
-    const bool ok = (gz | a | b) >= 0;
-    const T v = r[ok ? gz + a + b : 0];
-    pl[o1 * PT + o0] = ok ? v : T(0);
-  }
+    return (gz | a | b) >= 0 ? gz + a + b : -1;
+  };
+  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int i = gidx(e); return r[i >= 0 ? i : 0]; },
+                                       [&](int e, T v) {
+                                         const int o1 = e / N0, o0 = e - o1 * N0;
+                                         pl[o1 * PT + o0] = gidx(e) >= 0 ? v : T(0);
+                                       });
   __syncthreads();
   mfma_lines_cols<T, N0>(pl, N1, PT, 1, q.S[0]);  // rows: direction 0
   __syncthreads();
   mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.S[1]);  // columns: direction 1
   __syncthreads();
   T* dst = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
-  for (int e = tid; e < N0 * N1; e += nth) {
-    const int o1 = e / N0, o0 = e - o1 * N0;
-    dst[e] = pl[o1 * PT + o0];
-  }
+  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int o1 = e / N0; return pl[o1 * PT + e - o1 * N0]; },
+                                       [&](int e, T v) { dst[e] = v; });
 }
 
 // Stage B: block per (patch, o1).  Along direction 2: forward transform, scale
@@ -530,10 +560,9 @@ __global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ 
   const T l1 = q.lam[1][o1];
   T* slot = out + (int64_t)pid * Q::TS + (int64_t)o1 * N0;
   constexpr int64_t ZST = (int64_t)N0 * N1;
-  for (int e = tid; e < N0 * N2; e += nth) {
-    const int o2 = e / N0, o0 = e - o2 * N0;
-    pl[o2 * PT + o0] = slot[o2 * ZST + o0];
-  }
+  constexpr int NTB = big_b_threads<N2>();
+  big_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return slot[o2 * ZST + e - o2 * N0]; },
+                            [&](int e, T v) { const int o2 = e / N0; pl[o2 * PT + e - o2 * N0] = v; });
   __syncthreads();
   mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.S[2]);
   __syncthreads();
@@ -547,10 +576,8 @@ __global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ 
   __syncthreads();
   mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.ST[2]);
   __syncthreads();
-  for (int e = tid; e < N0 * N2; e += nth) {
-    const int o2 = e / N0, o0 = e - o2 * N0;
-    slot[o2 * ZST + o0] = pl[o2 * PT + o0];
-  }
+  big_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return pl[o2 * PT + e - o2 * N0]; },
+                            [&](int e, T v) { const int o2 = e / N0; slot[o2 * ZST + e - o2 * N0] = v; });
 }
 
 // Stage C: block per (patch, o2).  Backward transform along directions 1 and 0,
@@ -571,34 +598,34 @@ __global__ void __launch_bounds__(256) fdm_big_c(LevelDev<T> L, T* __restrict__ 
   for (int o = tid; o < N1; o += nth) w1[o] = q.w[1][o];
   const T w2 = q.w[2][o2];
   T* slot = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
-  for (int e = tid; e < N0 * N1; e += nth) {
-    const int o1 = e / N0, o0 = e - o1 * N0;
-    pl[o1 * PT + o0] = slot[e];
-  }
+  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { return slot[e]; },
+                                       [&](int e, T v) { const int o1 = e / N0; pl[o1 * PT + e - o1 * N0] = v; });
   __syncthreads();
   mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.ST[1]);
   __syncthreads();
   mfma_lines_cols<T, N0>(pl, N1, PT, 1, q.ST[0]);
   __syncthreads();
-  for (int e = tid; e < N0 * N1; e += nth) {
-    const int o1 = e / N0, o0 = e - o1 * N0;
-    slot[e] = w0[o0] * w1[o1] * w2 * pl[o1 * PT + o0];
-  }
+  big_copy<T, BIG_AC_THREADS, N0 * N1>(
+      [&](int e) {
+        const int o1 = e / N0, o0 = e - o1 * N0;
+        return w0[o0] * w1[o1] * w2 * pl[o1 * PT + o0];
+      },
+      [&](int e, T v) { slot[e] = v; });
 }
 
 template <class T, int NA, int NL, int ND>
 void fdm_big_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, int npz, hipStream_t s) {
   using Q = BigPatch<T, NA, NL, ND>;
   const int npatch = npx * npy * npz;
-  hipLaunchKernelGGL((fdm_big_a<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, r, out, npx,
-                     npy, npz);
+  hipLaunchKernelGGL((fdm_big_a<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(BIG_AC_THREADS), 0, s, L, r,
+                     out, npx, npy, npz);
   // stage B contracts only along direction 2: one wave per output column block
   // (3 for length 43: a fourth wave would idle through both passes)
-  constexpr int thb = 64 * ((Q::L2 + 15) / 16);
+  constexpr int thb = big_b_threads<Q::L2>();
   hipLaunchKernelGGL((fdm_big_b<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L1)), dim3(thb), 0, s, L, out, npx,
                      npy, npz);
-  hipLaunchKernelGGL((fdm_big_c<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(256), 0, s, L, out, npx,
-                     npy, npz);
+  hipLaunchKernelGGL((fdm_big_c<T, NA, NL, ND>), dim3(xcd_grid(npatch * Q::L2)), dim3(BIG_AC_THREADS), 0, s, L,
+                     out, npx, npy, npz);
 }
 
 template <class T, int NA, int NL>
