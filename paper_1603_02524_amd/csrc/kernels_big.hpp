@@ -11,6 +11,27 @@ namespace dgmg {
 
 constexpr int BIG_NP = 33;  // N_P of the largest order (P = 32)
 
+// Move n <= N values with every load of a thread issued before any of its
+// stores (a plain strided loop waits for each load before the next one
+// starts).  NT is the block size; ld(e) reads element e (called with e < n
+// only), st(e, v) writes it.
+template <class T, int NT, int N, class Ld, class St>
+__device__ __forceinline__ void big_copy(Ld ld, St st, int n = N) {
+  constexpr int C = (N + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    v[c] = ld(e < n ? e : n - 1);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    if (e < n) st(e, v[c]);
+  }
+}
+
 // ================================================================ operator apply
 // One launch per direction D (in order 0, 1, 2), one thread per line of that
 // direction, apply_lb<T>() lines per block: enough blocks to fill the chip
@@ -48,7 +69,7 @@ __global__ void __launch_bounds__(128) apply_big_face0(LevelDev<T> L, const T* _
   const int e = b / CH, c0 = (b - e * CH) * LB, t = c0 + tid;
   const int nlines = imin(LB, NLN - c0);
   const int64_t o = (int64_t)e * NE + (int64_t)c0 * NP;
-  for (int q = tid; q < nlines * NP; q += nth) sx[q] = x[o + q];
+  big_copy<T, LB, LB * NP>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
   __syncthreads();
   if (t < NLN) {
     T d0 = 0, dP = 0;
@@ -101,7 +122,7 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
   const int el = e + (nl >= 0 ? nl - m[D] : 0) * estride, er = e + (nr >= 0 ? nr - m[D] : 0) * estride;
   if constexpr (D == 0) {  // the block's lines are NP * nlines consecutive values
     const int64_t o = g0 + (int64_t)c0 * NP;
-    for (int q = tid; q < nlines * NP; q += nth) sx[q] = x[o + q];
+    big_copy<T, LB, SX>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
   }
   __syncthreads();
   double acc = 0.0;
@@ -179,7 +200,10 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
   if constexpr (D == 0) {
     __syncthreads();
     const int64_t o = g0 + (int64_t)c0 * NP;
-    for (int q = tid; q < nlines * NP; q += nth) y[o + q] = MODE == 1 ? f[o + q] - sx[q] : sx[q];
+    if constexpr (MODE == 1)
+      big_copy<T, LB, SX>([&](int q) { return f[o + q]; }, [&](int q, T v) { y[o + q] = v - sx[q]; }, nlines * NP);
+    else
+      for (int q = tid; q < nlines * NP; q += nth) y[o + q] = sx[q];
   }
   if constexpr (MODE == 2 && D == 2) {
     const double sum = block_sum(acc, red);
@@ -276,8 +300,8 @@ __global__ void __launch_bounds__(256) restrict_xy_kernel(const T* __restrict__ 
   if (e >= n_elem) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const T* src = tmp + b * PL;
-  for (int q = tid; q < PL; q += nth) pl[q] = src[q];
-  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = J[q];
+  big_copy<T, 256, PL>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
+  big_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
   __syncthreads();
   for (int q = tid; q < NPF * NPC; q += nth) {  // t1[j][i'] = sum_i J[i][i'] pl[j][i]
     const int j = q / NPC, ic = q - j * NPC;
@@ -308,8 +332,8 @@ __global__ void __launch_bounds__(256) prolong_xy_kernel(const T* __restrict__ J
   if (e >= n_elem) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const T* src = in + e * NEC + (int64_t)kc * NPC * NPC;
-  for (int q = tid; q < NPC * NPC; q += nth) pl[q] = src[q];
-  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = J[q];
+  big_copy<T, 256, NPC * NPC>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
+  big_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
   __syncthreads();
   for (int q = tid; q < NPC * NPF; q += nth) {  // t1[j'][i] = sum_i' J[i][i'] pl[j'][i']
     const int jc = q / NPF, i = q - jc * NPF;
@@ -477,27 +501,6 @@ constexpr int BIG_AC_THREADS = 256;
 template <int L2>
 constexpr int big_b_threads() {
   return 64 * ((L2 + 15) / 16);  // one wave per output column block of direction 2
-}
-
-// Move N values with every load of a thread issued before any of its stores
-// (a plain strided loop waits for each load before the next one starts).  NT
-// is the block size; ld(e) reads element e (called with e < N only), st(e, v)
-// writes it.
-template <class T, int NT, int N, class Ld, class St>
-__device__ __forceinline__ void big_copy(Ld ld, St st) {
-  constexpr int C = (N + NT - 1) / NT;
-  const int tid = threadIdx.x;
-  T v[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int e = tid + c * NT;
-    v[c] = ld(e < N ? e : N - 1);
-  }
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int e = tid + c * NT;
-    if (e < N) st(e, v[c]);
-  }
 }
 
 // Stage A: block per (patch, o2).  Gather the plane o2 of R_s r, forward
