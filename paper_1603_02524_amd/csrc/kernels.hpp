@@ -132,6 +132,27 @@ __device__ __forceinline__ P* sgpr_ptr(P* p) {
   return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
 }
 
+// Move n <= N values with every load of a thread issued before any of its
+// stores (a plain strided loop waits for each load before the next one
+// starts).  NT is the block size; ld(e) reads element e (called with e < n
+// only), st(e, v) writes it.
+template <class T, int NT, int N, class Ld, class St>
+__device__ __forceinline__ void staged_copy(Ld ld, St st, int n = N) {
+  constexpr int C = (N + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    v[c] = ld(e < n ? e : n - 1);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int e = tid + c * NT;
+    if (e < n) st(e, v[c]);
+  }
+}
+
 // Own elements staged in LDS (coalesced loads) when the tiles are small: the
 // lines of the block's own elements are then read from LDS and only the
 // neighbours' lines from global memory.  A line along direction 0 is contiguous,
@@ -1096,6 +1117,7 @@ int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf,
 // Element-local tensor-product contractions with the embedded interpolation J
 // (NPf x NPc).  RESTRICT: out_c = (J^T x J^T x J^T) in_f.  Otherwise:
 // out_f += (J x J x J) in_c.  One block per group of elements; LDS ping-pong.
+constexpr int XFER_THREADS = 256;  // block size of transfer_kernel (its copies unroll over it)
 template <int NPF, int DIM>
 constexpr int xfer_epb() {
   return imax(1, 512 / ipow(NPF, DIM));
@@ -1144,12 +1166,13 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
   __shared__ T sJ[NPF * NPC];
   const int e0 = blockIdx.x * EPB;
   const int ne = imin(EPB, n_elem - e0);
-  const int tid = threadIdx.x, nth = blockDim.x;
-  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = J[q];
-  for (int q = tid; q < ne * NEI; q += nth) {
-    const int el = q / NEI, r = q - el * NEI;
-    bufA[el * NEF + r] = in[(int64_t)e0 * NEI + q];  // per-element stride NEF in LDS
-  }
+  staged_copy<T, XFER_THREADS, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
+  staged_copy<T, XFER_THREADS, EPB * NEI>([&](int q) { return in[(int64_t)e0 * NEI + q]; },
+                                          [&](int q, T v) {
+                                            const int el = q / NEI;
+                                            bufA[el * NEF + q - el * NEI] = v;  // per-element stride NEF in LDS
+                                          },
+                                          ne * NEI);
   __syncthreads();
   xfer_pass<T, DIM, NIN, NOUT, NEF, 0, RESTRICT, NPC>(sJ, bufA, bufB, ne);
   __syncthreads();
@@ -1161,13 +1184,16 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
     __syncthreads();
     res = bufB;
   }
-  for (int q = tid; q < ne * NEO; q += nth) {
-    const int el = q / NEO, r = q - el * NEO;
-    if (RESTRICT)
-      out[(int64_t)e0 * NEO + q] = res[el * NEF + r];
-    else
-      out[(int64_t)e0 * NEO + q] += res[el * NEF + r];
-  }
+  const auto rv = [&](int q) {
+    const int el = q / NEO;
+    return res[el * NEF + q - el * NEO];
+  };
+  T* o = out + (int64_t)e0 * NEO;
+  if constexpr (RESTRICT)
+    staged_copy<T, XFER_THREADS, EPB * NEO>(rv, [&](int q, T v) { o[q] = v; }, ne * NEO);
+  else
+    staged_copy<T, XFER_THREADS, EPB * NEO>([&](int q) { return o[q]; }, [&](int q, T v) { o[q] = v + rv(q); },
+                                            ne * NEO);
 }
 
 template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
@@ -1178,7 +1204,7 @@ int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* ac
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)transfer_kernel<T, DIM, NPF, NPC, RESTRICT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT>), dim3(nb), dim3(256), shm, s, J,
+  hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT>), dim3(nb), dim3(XFER_THREADS), shm, s, J,
                      n_elem, in, out, active);
   return 0;
 }

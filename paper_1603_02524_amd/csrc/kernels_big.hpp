@@ -11,27 +11,6 @@ namespace dgmg {
 
 constexpr int BIG_NP = 33;  // N_P of the largest order (P = 32)
 
-// Move n <= N values with every load of a thread issued before any of its
-// stores (a plain strided loop waits for each load before the next one
-// starts).  NT is the block size; ld(e) reads element e (called with e < n
-// only), st(e, v) writes it.
-template <class T, int NT, int N, class Ld, class St>
-__device__ __forceinline__ void big_copy(Ld ld, St st, int n = N) {
-  constexpr int C = (N + NT - 1) / NT;
-  const int tid = threadIdx.x;
-  T v[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int e = tid + c * NT;
-    v[c] = ld(e < n ? e : n - 1);
-  }
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int e = tid + c * NT;
-    if (e < n) st(e, v[c]);
-  }
-}
-
 // ================================================================ operator apply
 // One launch per direction D (in order 0, 1, 2), one thread per line of that
 // direction, apply_lb<T>() lines per block: enough blocks to fill the chip
@@ -69,7 +48,7 @@ __global__ void __launch_bounds__(128) apply_big_face0(LevelDev<T> L, const T* _
   const int e = b / CH, c0 = (b - e * CH) * LB, t = c0 + tid;
   const int nlines = imin(LB, NLN - c0);
   const int64_t o = (int64_t)e * NE + (int64_t)c0 * NP;
-  big_copy<T, LB, LB * NP>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
+  staged_copy<T, LB, LB * NP>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
   __syncthreads();
   if (t < NLN) {
     T d0 = 0, dP = 0;
@@ -122,7 +101,7 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
   const int el = e + (nl >= 0 ? nl - m[D] : 0) * estride, er = e + (nr >= 0 ? nr - m[D] : 0) * estride;
   if constexpr (D == 0) {  // the block's lines are NP * nlines consecutive values
     const int64_t o = g0 + (int64_t)c0 * NP;
-    big_copy<T, LB, SX>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
+    staged_copy<T, LB, SX>([&](int q) { return x[o + q]; }, [&](int q, T v) { sx[q] = v; }, nlines * NP);
   }
   __syncthreads();
   double acc = 0.0;
@@ -201,7 +180,7 @@ __global__ void __launch_bounds__(128) apply_big_kernel(LevelDev<T> L, const T* 
     __syncthreads();
     const int64_t o = g0 + (int64_t)c0 * NP;
     if constexpr (MODE == 1)
-      big_copy<T, LB, SX>([&](int q) { return f[o + q]; }, [&](int q, T v) { y[o + q] = v - sx[q]; }, nlines * NP);
+      staged_copy<T, LB, SX>([&](int q) { return f[o + q]; }, [&](int q, T v) { y[o + q] = v - sx[q]; }, nlines * NP);
     else
       for (int q = tid; q < nlines * NP; q += nth) y[o + q] = sx[q];
   }
@@ -300,8 +279,8 @@ __global__ void __launch_bounds__(256) restrict_xy_kernel(const T* __restrict__ 
   if (e >= n_elem) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const T* src = tmp + b * PL;
-  big_copy<T, 256, PL>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
-  big_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
+  staged_copy<T, 256, PL>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
+  staged_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
   __syncthreads();
   for (int q = tid; q < NPF * NPC; q += nth) {  // t1[j][i'] = sum_i J[i][i'] pl[j][i]
     const int j = q / NPC, ic = q - j * NPC;
@@ -332,8 +311,8 @@ __global__ void __launch_bounds__(256) prolong_xy_kernel(const T* __restrict__ J
   if (e >= n_elem) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const T* src = in + e * NEC + (int64_t)kc * NPC * NPC;
-  big_copy<T, 256, NPC * NPC>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
-  big_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
+  staged_copy<T, 256, NPC * NPC>([&](int q) { return src[q]; }, [&](int q, T v) { pl[q] = v; });
+  staged_copy<T, 256, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
   __syncthreads();
   for (int q = tid; q < NPC * NPF; q += nth) {  // t1[j'][i] = sum_i' J[i][i'] pl[j'][i']
     const int jc = q / NPF, i = q - jc * NPF;
@@ -529,7 +508,7 @@ __global__ void __launch_bounds__(256) fdm_big_a(LevelDev<T> L, const T* __restr
     const int a = g0[o0], b = g1[o1];
     return (gz | a | b) >= 0 ? gz + a + b : -1;
   };
-  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int i = gidx(e); return r[i >= 0 ? i : 0]; },
+  staged_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int i = gidx(e); return r[i >= 0 ? i : 0]; },
                                        [&](int e, T v) {
                                          const int o1 = e / N0, o0 = e - o1 * N0;
                                          pl[o1 * PT + o0] = gidx(e) >= 0 ? v : T(0);
@@ -540,7 +519,7 @@ __global__ void __launch_bounds__(256) fdm_big_a(LevelDev<T> L, const T* __restr
   mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.S[1]);  // columns: direction 1
   __syncthreads();
   T* dst = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
-  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int o1 = e / N0; return pl[o1 * PT + e - o1 * N0]; },
+  staged_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { const int o1 = e / N0; return pl[o1 * PT + e - o1 * N0]; },
                                        [&](int e, T v) { dst[e] = v; });
 }
 
@@ -564,7 +543,7 @@ __global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ 
   T* slot = out + (int64_t)pid * Q::TS + (int64_t)o1 * N0;
   constexpr int64_t ZST = (int64_t)N0 * N1;
   constexpr int NTB = big_b_threads<N2>();
-  big_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return slot[o2 * ZST + e - o2 * N0]; },
+  staged_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return slot[o2 * ZST + e - o2 * N0]; },
                             [&](int e, T v) { const int o2 = e / N0; pl[o2 * PT + e - o2 * N0] = v; });
   __syncthreads();
   mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.S[2]);
@@ -579,7 +558,7 @@ __global__ void __launch_bounds__(256) fdm_big_b(LevelDev<T> L, T* __restrict__ 
   __syncthreads();
   mfma_lines_cols<T, N2>(pl, N0, 1, PT, q.ST[2]);
   __syncthreads();
-  big_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return pl[o2 * PT + e - o2 * N0]; },
+  staged_copy<T, NTB, N0 * N2>([&](int e) { const int o2 = e / N0; return pl[o2 * PT + e - o2 * N0]; },
                             [&](int e, T v) { const int o2 = e / N0; slot[o2 * ZST + e - o2 * N0] = v; });
 }
 
@@ -601,14 +580,14 @@ __global__ void __launch_bounds__(256) fdm_big_c(LevelDev<T> L, T* __restrict__ 
   for (int o = tid; o < N1; o += nth) w1[o] = q.w[1][o];
   const T w2 = q.w[2][o2];
   T* slot = out + (int64_t)pid * Q::TS + (int64_t)o2 * N0 * N1;
-  big_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { return slot[e]; },
+  staged_copy<T, BIG_AC_THREADS, N0 * N1>([&](int e) { return slot[e]; },
                                        [&](int e, T v) { const int o1 = e / N0; pl[o1 * PT + e - o1 * N0] = v; });
   __syncthreads();
   mfma_lines_cols<T, N1>(pl, N0, 1, PT, q.ST[1]);
   __syncthreads();
   mfma_lines_cols<T, N0>(pl, N1, PT, 1, q.ST[0]);
   __syncthreads();
-  big_copy<T, BIG_AC_THREADS, N0 * N1>(
+  staged_copy<T, BIG_AC_THREADS, N0 * N1>(
       [&](int e) {
         const int o1 = e / N0, o0 = e - o1 * N0;
         return w0[o0] * w1[o1] * w2 * pl[o1 * PT + o0];
