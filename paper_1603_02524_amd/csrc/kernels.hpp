@@ -401,8 +401,12 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       const int q = tid + j * nth;
       if (q < ne * NE) out(q, pre[j]);
     }
+  } else if constexpr (MODE == 0) {
+    for (int q = tid; q < ne * NE; q += nth) out(q, T(0));
   } else {
-    for (int q = tid; q < ne * NE; q += nth) out(q, MODE == 1 ? f[g0 + q] : (MODE == 2 ? x[g0 + q] : T(0)));
+    // every load of f (x) issued before the sums that use them
+    const T* __restrict__ src = MODE == 1 ? f : x;
+    staged_copy<T, TH, EPB * NE>([&](int q) { return src[g0 + q]; }, [&](int q, T v) { out(q, v); }, ne * NE);
   }
   if (MODE == 2) {
     const double s = block_sum(acc, red);
