@@ -1082,10 +1082,12 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
       for (int b = 0; b < MAXC; ++b)
 #pragma unroll
         for (int a = 0; a < MAXC; ++a) {
-          // invalid candidates read buf[0] (valid) and are dropped from the sum
+          // invalid candidates are not loaded (their lanes are masked off: on
+          // average about half of the 2 x 2 x 2 slots are empty) and add 0
           const bool ok = c < nz && b < ny && a < nx;
-          const int64_t ad = ok ? cadr[el][2][k][c] + cadr[el][1][j][b] + cadr[el][0][i][a] : 0;
-          v[c][b][a] = buf[ad];
+          T val = T(0);
+          if (ok) val = buf[cadr[el][2][k][c] + cadr[el][1][j][b] + cadr[el][0][i][a]];
+          v[c][b][a] = val;
         }
     T s = 0;
 #pragma unroll
