@@ -660,6 +660,21 @@ int k_transfer(dgmg_handle* h, int l, bool restr, const T* in, T* out) {
   return check_hip(h, "transfer");
 }
 
+// f_{l-1} = restriction of (f_l - A_l u_l): one fused launch where it is built
+// (the fine residual then never leaves LDS), else the residual into r_scratch
+// and the transfer.  Both give the same values.
+template <class T>
+int k_residual_restrict(dgmg_handle* h, int l, const T* u, const T* f, T* r_scratch, T* fc) {
+  const LevelDev<T>& L = LD<T>(h, l);
+  T* scratch = (T*)h->patch;
+  int rc = L.dim == 3 ? Kern<T, 3>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream)
+                      : Kern<T, 2>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream);
+  if (rc == 0) return check_hip(h, "residual restriction");
+  rc = k_apply<T>(h, l, 1, u, f, r_scratch, nullptr, nullptr);
+  if (rc) return rc;
+  return k_transfer<T>(h, l, true, r_scratch, fc);
+}
+
 template <class T>
 void k_fill_v(dgmg_handle* h, T* a, int64_t n, T v = T(0)) {
   hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, v, n, h->active);
@@ -751,9 +766,7 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
     T* rl = (T*)h->buf[l].r;
     int rc = k_smooth<T>(h, l, u[l], f[l], ns(l, 0), rl, pre);
     if (rc) return rc;
-    rc = k_apply<T>(h, l, 1, u[l], f[l], rl, nullptr, nullptr);
-    if (rc) return rc;
-    rc = k_transfer<T>(h, l, true, rl, f[l - 1]);
+    rc = k_residual_restrict<T>(h, l, u[l], f[l], rl, f[l - 1]);
     if (rc) return rc;
   }
   int rc = k_coarse<T>(h, f[0], u[0]);

@@ -29,7 +29,7 @@ int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, 
 #define DGMG_CASE(NP)                                                              \
   case NP:                                                                         \
     if constexpr (DIM == 3 && NP == BIG_NP)                                        \
-      return apply_big_launch<T, NP>(L, mode, x, f, y, scratch, part, nblk, s);    \
+      return mode == 3 ? -4 : apply_big_launch<T, NP>(L, mode, x, f, y, scratch, part, nblk, s); \
     else                                                                           \
       return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
     DGMG_NP_LIST(DGMG_CASE)

@@ -97,7 +97,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ================================================================ operator apply
-// y = A x (MODE 0), y = f - A x (MODE 1), y = A x plus per-block partial x.y (MODE 2).
+// y = A x (MODE 0), y = f - A x (MODE 1), y = A x plus per-block partial x.y (MODE 2),
+// or the restriction of f - A x to the next coarser level, y = (J^T x J^T x J^T)(f - A x)
+// per element (MODE 3: the V-cycle's residual and restriction in one pass; the
+// fine residual stays in LDS and the transfer's contraction passes run on it).
 // One thread owns one line of one element in one direction, and the lines of
 // all directions run at once (their global loads overlap instead of forming
 // one latency chain per direction).  Each node receives exactly one
@@ -178,6 +181,10 @@ struct ApplyLine {
   T wlv[NP], wrv[NP];
 };
 
+template <class T, int DIM, int NIN, int NOUT, int NEF, int D, bool RESTRICT, int NPC>
+__device__ __forceinline__ void xfer_pass(const T* __restrict__ sJ, const T* __restrict__ src,
+                                          T* __restrict__ dst, int ne);
+
 template <class T, int DIM, int NP, int MODE>
 __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __restrict__ x,
                                                      const T* __restrict__ f, T* __restrict__ y,
@@ -207,6 +214,12 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
     for (int q = tid; q < NP * NP; q += nth) sLsL[q] = L.Ls[q];
     __syncthreads();
   }
+  // MODE 3: the interpolation matrix J (NP x NPC, row-major) of the restriction
+  constexpr int NPC = (NP - 1) / 2 + 1;  // N_P of the next coarser level, P_c = floor(P / 2)
+  static_assert(MODE != 3 || STAGE, "the fused restriction needs the own-element LDS buffer");
+  __shared__ T sJx[MODE == 3 ? NP * NPC : 1];
+  if constexpr (MODE == 3)
+    for (int q = tid; q < NP * NPC; q += nth) sJx[q] = L.J[q];
   using CT = const __attribute__((address_space(4))) T;
   CT* __restrict__ Ls = (CT*)L.Ls;
   CT* __restrict__ D0 = (CT*)L.D;
@@ -232,7 +245,7 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   constexpr bool PREF = MODE != 0 && NP <= 9;
   T pre[PREF ? FQ : 1];
   if constexpr (PREF) {
-    const T* __restrict__ src = MODE == 1 ? f : x;
+    const T* __restrict__ src = (MODE == 1 || MODE == 3) ? f : x;
 #pragma unroll
     for (int j = 0; j < FQ; ++j) {
       const int q = tid + j * nth;
@@ -390,6 +403,8 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
       y[g0 + q] = val;
     } else if (MODE == 1) {
       y[g0 + q] = other - val;
+    } else if (MODE == 3) {
+      sx[q] = other - val;  // the own elements' x are no longer needed
     } else {
       y[g0 + q] = val;
       acc += (double)other * (double)val;
@@ -405,12 +420,35 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
     for (int q = tid; q < ne * NE; q += nth) out(q, T(0));
   } else {
     // every load of f (x) issued before the sums that use them
-    const T* __restrict__ src = MODE == 1 ? f : x;
+    const T* __restrict__ src = (MODE == 1 || MODE == 3) ? f : x;
     staged_copy<T, TH, EPB * NE>([&](int q) { return src[g0 + q]; }, [&](int q, T v) { out(q, v); }, ne * NE);
   }
   if (MODE == 2) {
     const double s = block_sum(acc, red);
     if (tid == 0) part[blk] = s;
+  }
+  if constexpr (MODE == 3) {
+    // the transfer kernel's restriction passes, on the residual in LDS (the
+    // direction tiles serve as the two pass buffers); y is the coarse vector
+    constexpr int NEC = ipow(NPC, DIM);
+    __syncthreads();
+    T* bA = sy;
+    T* bB = sy + EPB * NE;
+    xfer_pass<T, DIM, NP, NPC, NE, 0, true, NPC>(sJx, sx, bA, ne);
+    __syncthreads();
+    xfer_pass<T, DIM, NP, NPC, NE, 1, true, NPC>(sJx, bA, bB, ne);
+    __syncthreads();
+    const T* res = bB;
+    if constexpr (DIM == 3) {
+      xfer_pass<T, DIM, NP, NPC, NE, 2, true, NPC>(sJx, bB, bA, ne);
+      __syncthreads();
+      res = bA;
+    }
+    T* yc = y + (int64_t)e0 * NEC;
+    for (int q = tid; q < ne * NEC; q += nth) {
+      const int el = q / NEC;
+      yc[q] = res[el * NE + q - el * NEC];
+    }
   }
 }
 
@@ -428,9 +466,20 @@ int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, d
   } else if (mode == 1) {
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 1>), grid, block, shm, s, L, x, f, y, part, nblk);
-  } else {
+  } else if (mode == 2) {
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 2>), grid, block, shm, s, L, x, f, y, part, nblk);
+  } else {
+    // fused residual + restriction: own elements staged in LDS and the coarse
+    // level's order following P_c = floor(P / 2); otherwise the caller runs the
+    // two steps
+    if constexpr (apply_stage_own<NP, DIM>()) {
+      if (L.NPc != (NP - 1) / 2 + 1 || !L.J) return -4;
+      if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 3>), grid, block, shm, s, L, x, f, y, part, nblk);
+    } else {
+      return -4;
+    }
   }
   return 0;
 }
@@ -1218,7 +1267,9 @@ int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* ac
 // ================================================================ dispatch (instantiated per T, DIM)
 template <class T, int DIM>
 struct Kern {
-  // scratch: apply_big_scratch(n_elem, NP) elements (3D levels with NP = 33 only)
+  // scratch: apply_big_scratch(n_elem, NP) elements (3D levels with NP = 33 only).
+  // mode 3 (residual restricted to the coarser level, y coarse) returns -4 where
+  // it is not built (large elements): the caller then runs mode 1 and transfer.
   static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
                    int* nblk, hipStream_t s);
   static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
