@@ -98,17 +98,21 @@ __global__ void __launch_bounds__(VEC_THREADS) k_sum_abs(const double* __restric
   }
 }
 
-// z.(r - r_old) and z.r partials.
-__global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const double* __restrict__ z,
+// z.(r - r_old) and z.r partials.  TZ = float: z is the FP32 V-cycle output,
+// widened here and also stored as the FP64 z (zout) in the same pass.
+template <class TZ>
+__global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const TZ* __restrict__ z,
                                                         const double* __restrict__ r,
                                                         const double* __restrict__ ro, int64_t n,
                                                         double* __restrict__ part1,
-                                                        double* __restrict__ part2, const int* act) {
+                                                        double* __restrict__ part2, double* __restrict__ zout,
+                                                        const int* act) {
   if (inactive(act)) return;
   __shared__ double red[16];
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double zi = z[i], ri = r[i];
+    const double zi = (double)z[i], ri = r[i];
+    if constexpr (sizeof(TZ) != sizeof(double)) zout[i] = zi;
     s1 += zi * (ri - ro[i]);
     s2 += zi * ri;
   }
@@ -781,7 +785,9 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
 }
 
 // Preconditioner z = MG(r) on FP64 top-level vectors.
-int precond(dgmg_handle* h, const double* r, double* z) {
+// widen = false (mixed precision only): the FP32 result stays in the top
+// level's u buffer and z is not written (the caller widens it itself).
+int precond(dgmg_handle* h, const double* r, double* z, bool widen = true) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
   if (!mixed(h)) return k_vcycle<double>(h, r, z);
@@ -790,7 +796,8 @@ int precond(dgmg_handle* h, const double* r, double* z) {
   hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, r, rf, n, h->active);
   int rc = k_vcycle<float>(h, rf, zf);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, zf, z, n, h->active);
+  if (widen)
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, zf, z, n, h->active);
   return check_hip(h, "precond convert");
 }
 
@@ -841,10 +848,15 @@ int pcg_phase_a(dgmg_handle* h, double* x) {
 int pcg_phase_b(dgmg_handle* h) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
-  int rc = precond(h, h->pr, h->pz);
+  // mixed precision: z is widened from the FP32 V-cycle output by the dot-product pass
+  int rc = precond(h, h->pr, h->pz, !mixed(h));
   if (rc) return rc;
-  hipLaunchKernelGGL(k_dot_zr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro, n,
-                     h->part, h->part2, h->active);
+  if (mixed(h))
+    hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream,
+                       (const float*)h->buf[L].u, h->pr, h->pro, n, h->part, h->part2, h->pz, h->active);
+  else
+    hipLaunchKernelGGL((k_dot_zr<double>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro,
+                       n, h->part, h->part2, (double*)nullptr, h->active);
   hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, h->part2, RED_BLOCKS,
                      h->scal, h->active);
   hipLaunchKernelGGL(k_update_p, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, h->pz, h->pr, h->pro,
