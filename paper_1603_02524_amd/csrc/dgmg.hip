@@ -125,13 +125,15 @@ __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const TZ* __restrict__ z
   }
 }
 
-// alpha = delta / (p.q); x += alpha p; r -= alpha q; partial r.r
+// alpha = delta / (p.q); x += alpha p; r -= alpha q; partial r.r; rf (if not
+// null) = r rounded to FP32, the input of the mixed-precision V-cycle
 __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ x, double* __restrict__ r,
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q,
                                                            const double* __restrict__ delta,
                                                            const double* __restrict__ pq, int64_t n,
-                                                           double* __restrict__ part, const int* act) {
+                                                           double* __restrict__ part, float* __restrict__ rf,
+                                                           const int* act) {
   if (inactive(act)) return;
   __shared__ double red[16];
   const double alpha = delta[0] / pq[0];
@@ -140,6 +142,7 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (rf) rf[i] = (float)ri;
     s += ri * ri;
   }
   s = block_sum(s, red);
@@ -787,13 +790,15 @@ int k_vcycle(dgmg_handle* h, const T* r, T* z) {
 // Preconditioner z = MG(r) on FP64 top-level vectors.
 // widen = false (mixed precision only): the FP32 result stays in the top
 // level's u buffer and z is not written (the caller widens it itself).
-int precond(dgmg_handle* h, const double* r, double* z, bool widen = true) {
+// narrow = false: the FP32 copy of r is already in the top level's f buffer.
+int precond(dgmg_handle* h, const double* r, double* z, bool widen = true, bool narrow = true) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
   if (!mixed(h)) return k_vcycle<double>(h, r, z);
   float* rf = (float*)h->buf[L].f;
   float* zf = (float*)h->buf[L].u;
-  hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, r, rf, n, h->active);
+  if (narrow)
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, r, rf, n, h->active);
   int rc = k_vcycle<float>(h, rf, zf);
   if (rc) return rc;
   if (widen)
@@ -838,8 +843,9 @@ int pcg_phase_a(dgmg_handle* h, double* x) {
   int rc = k_apply<double>(h, L, 2, h->pp, nullptr, h->pq, h->part, &nb);
   if (rc) return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, nb, h->scal + S_PQ, h->active);
+  float* rf = mixed(h) ? (float*)h->buf[L].f : nullptr;  // the next V-cycle's FP32 input
   hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, h->pr, h->pp, h->pq,
-                     h->scal + S_DELTA, h->scal + S_PQ, n, h->part2, h->active);
+                     h->scal + S_DELTA, h->scal + S_PQ, n, h->part2, rf, h->active);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, rr_slot(h), h->active);
   return check_hip(h, "pcg phase a");
 }
@@ -849,7 +855,8 @@ int pcg_phase_b(dgmg_handle* h) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
   // mixed precision: z is widened from the FP32 V-cycle output by the dot-product pass
-  int rc = precond(h, h->pr, h->pz, !mixed(h));
+  // (r's FP32 copy was written by phase a's update)
+  int rc = precond(h, h->pr, h->pz, !mixed(h), !mixed(h));
   if (rc) return rc;
   if (mixed(h))
     hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream,
