@@ -99,20 +99,18 @@ __global__ void __launch_bounds__(VEC_THREADS) k_sum_abs(const double* __restric
 }
 
 // z.(r - r_old) and z.r partials.  TZ = float: z is the FP32 V-cycle output,
-// widened here and also stored as the FP64 z (zout) in the same pass.
+// widened to FP64 as it is read (here and in k_update_p).
 template <class TZ>
 __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const TZ* __restrict__ z,
                                                         const double* __restrict__ r,
                                                         const double* __restrict__ ro, int64_t n,
                                                         double* __restrict__ part1,
-                                                        double* __restrict__ part2, double* __restrict__ zout,
-                                                        const int* act) {
+                                                        double* __restrict__ part2, const int* act) {
   if (inactive(act)) return;
   __shared__ double red[16];
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double zi = (double)z[i], ri = r[i];
-    if constexpr (sizeof(TZ) != sizeof(double)) zout[i] = zi;
     s1 += zi * (ri - ro[i]);
     s2 += zi * ri;
   }
@@ -149,8 +147,9 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// p = z + beta p; r_old = r
-__global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p, const double* __restrict__ z,
+// p = z + beta p; r_old = r (z FP64, or the FP32 V-cycle output widened)
+template <class TZ>
+__global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p, const TZ* __restrict__ z,
                                                           const double* __restrict__ r,
                                                           double* __restrict__ ro,
                                                           const double* __restrict__ beta_p,
@@ -158,7 +157,7 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p
   if (inactive(act)) return;
   const double beta = beta_p[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    p[i] = z[i] + beta * p[i];
+    p[i] = (double)z[i] + beta * p[i];
     ro[i] = r[i];
   }
 }
@@ -854,20 +853,27 @@ int pcg_phase_a(dgmg_handle* h, double* x) {
 int pcg_phase_b(dgmg_handle* h) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
-  // mixed precision: z is widened from the FP32 V-cycle output by the dot-product pass
-  // (r's FP32 copy was written by phase a's update)
-  int rc = precond(h, h->pr, h->pz, !mixed(h), !mixed(h));
+  // mixed precision: the dot products and the direction update read the FP32
+  // V-cycle output and widen it (no FP64 z); r's FP32 copy was written by
+  // phase a's update
+  const bool mx = mixed(h);
+  int rc = precond(h, h->pr, h->pz, !mx, !mx);
   if (rc) return rc;
-  if (mixed(h))
-    hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream,
-                       (const float*)h->buf[L].u, h->pr, h->pro, n, h->part, h->part2, h->pz, h->active);
+  const float* zf = (const float*)h->buf[L].u;
+  if (mx)
+    hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, zf, h->pr, h->pro, n,
+                       h->part, h->part2, h->active);
   else
     hipLaunchKernelGGL((k_dot_zr<double>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro,
-                       n, h->part, h->part2, (double*)nullptr, h->active);
+                       n, h->part, h->part2, h->active);
   hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, h->part2, RED_BLOCKS,
                      h->scal, h->active);
-  hipLaunchKernelGGL(k_update_p, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, h->pz, h->pr, h->pro,
-                     h->scal + S_BETA, n, h->active);
+  if (mx)
+    hipLaunchKernelGGL((k_update_p<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, zf, h->pr, h->pro,
+                       h->scal + S_BETA, n, h->active);
+  else
+    hipLaunchKernelGGL((k_update_p<double>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp,
+                       (const double*)h->pz, h->pr, h->pro, h->scal + S_BETA, n, h->active);
   return check_hip(h, "pcg phase b");
 }
 
