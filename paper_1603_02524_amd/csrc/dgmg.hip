@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -328,6 +329,10 @@ struct dgmg_handle {
   float tune_ms[MAXL][NKIND] = {};
   // timing of the top-level patch solves
   bool timing = false;
+  // V-cycle residual + restriction in one launch where built; the environment
+  // variable DGMG_NO_FUSED_RESTRICTION at setup selects the two-step path
+  // (same values; kept for comparison)
+  bool fuse_restrict = true;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   std::vector<double> ev_flops, ev_bytes;
   double t_ms = 0, t_flops = 0, t_bytes = 0;
@@ -673,8 +678,10 @@ template <class T>
 int k_residual_restrict(dgmg_handle* h, int l, const T* u, const T* f, T* r_scratch, T* fc) {
   const LevelDev<T>& L = LD<T>(h, l);
   T* scratch = (T*)h->patch;
-  int rc = L.dim == 3 ? Kern<T, 3>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream)
-                      : Kern<T, 2>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream);
+  int rc = -4;
+  if (h->fuse_restrict)
+    rc = L.dim == 3 ? Kern<T, 3>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream)
+                    : Kern<T, 2>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream);
   if (rc == 0) return check_hip(h, "residual restriction");
   rc = k_apply<T>(h, l, 1, u, f, r_scratch, nullptr, nullptr);
   if (rc) return rc;
@@ -1084,6 +1091,7 @@ int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out) {
   int rc = validate_setup(g, o, sp);
   if (rc) return rc;
   dgmg_handle* h = new dgmg_handle();
+  h->fuse_restrict = std::getenv("DGMG_NO_FUSED_RESTRICTION") == nullptr;
   h->sp = sp;
   h->opts = *o;
   std::string e = build_levels(sp, h->lv);

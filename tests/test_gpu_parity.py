@@ -4,6 +4,8 @@ element, on seeded grids whose element counts leave ragged final blocks.
 Tolerances: FP64 results within 1e-12 relative (operator, transfers) and the
 solver within the 1e-10 relative bound of the FP64 path; FP32 kernels within a
 bound derived from float rounding (see the individual tests)."""
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -249,6 +251,37 @@ def test_mass_and_manufactured_c1():
     err = np.abs(xs - (np.sin(np.pi * X) * np.sin(np.pi * Y)).reshape(-1)).max()
     assert err < 2e-4
     S.close()
+
+
+@pytest.mark.parametrize("cid", ["3d_dir_ip_p8_fa", "2d_dir_ip_p4_ea", "3d_dir_ldg_p4_ea", "3d_per_ip_p6_fa"])
+def test_fused_residual_restriction_is_bitwise_two_step(cid, monkeypatch):
+    """The V-cycle's residual + restriction in one launch gives the same bits as
+    the residual followed by the separate transfer (selected at setup by
+    DGMG_NO_FUSED_RESTRICTION), in FP64 and in the FP32 V-cycle."""
+    g, m = case(cid)
+    rng = np.random.default_rng(23)
+    for prec in ("fp64", "mixed"):
+        mm = replace(m, precision=prec)
+        S1 = D.Solver(g, mm)
+        monkeypatch.setenv("DGMG_NO_FUSED_RESTRICTION", "1")
+        S2 = D.Solver(g, mm)
+        monkeypatch.delenv("DGMG_NO_FUSED_RESTRICTION")
+        try:
+            n = S1.n_dof()
+            r = rng.standard_normal(n)
+            if all(g.periodic):
+                r -= r.mean()
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            z1 = S1.vcycle(_dev(r, dt))
+            z2 = S2.vcycle(_dev(r, dt))
+            assert torch.equal(z1, z2), (cid, prec)
+            x1, x2 = _dev(np.zeros(n)), _dev(np.zeros(n))
+            st1 = S1.solve(_dev(r), x1)
+            st2 = S2.solve(_dev(r), x2)
+            assert st1["iterations"] == st2["iterations"] and torch.equal(x1, x2), (cid, prec)
+        finally:
+            S1.close()
+            S2.close()
 
 
 def test_zero_rhs_and_exact_guess():
