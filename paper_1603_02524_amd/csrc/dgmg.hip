@@ -57,7 +57,9 @@ __global__ void __launch_bounds__(VEC_THREADS) k_finalize(const double* __restri
 
 // Phase-b scalars in one block: n = z.(r - r_old) and z.r from their partials
 // (each in a fixed order), then beta = n / delta with the previous delta, and
-// delta <- z.r.  scal slots: 0 delta, 1 beta, 4 n, 5 z.r.
+// delta <- z.r; from now on r_old enters n with weight 1 (slot 6, 0 before the
+// first direction update: r_old = 0 initially).  scal slots: 0 delta, 1 beta,
+// 4 n, 5 z.r, 6 r_old weight.
 __global__ void __launch_bounds__(VEC_THREADS) k_finalize_beta(const double* __restrict__ part1,
                                                                const double* __restrict__ part2, int np,
                                                                double* __restrict__ scal, const int* act) {
@@ -76,6 +78,7 @@ __global__ void __launch_bounds__(VEC_THREADS) k_finalize_beta(const double* __r
     scal[5] = s2;
     scal[1] = s1 / scal[0];
     scal[0] = s2;
+    scal[6] = 1.0;
   }
 }
 
@@ -104,15 +107,17 @@ __global__ void __launch_bounds__(VEC_THREADS) k_sum_abs(const double* __restric
 template <class TZ>
 __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const TZ* __restrict__ z,
                                                         const double* __restrict__ r,
-                                                        const double* __restrict__ ro, int64_t n,
+                                                        const double* __restrict__ ro,
+                                                        const double* __restrict__ ro_weight, int64_t n,
                                                         double* __restrict__ part1,
                                                         double* __restrict__ part2, const int* act) {
   if (inactive(act)) return;
   __shared__ double red[16];
+  const double wo = ro_weight[0];  // 0 before the first direction update (r - 0 r_old = r exactly)
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double zi = (double)z[i], ri = r[i];
-    s1 += zi * (ri - ro[i]);
+    s1 += zi * (ri - wo * ro[i]);
     s2 += zi * ri;
   }
   s1 = block_sum(s1, red);
@@ -124,9 +129,10 @@ __global__ void __launch_bounds__(VEC_THREADS) k_dot_zr(const TZ* __restrict__ z
   }
 }
 
-// alpha = delta / (p.q); x += alpha p; r -= alpha q; partial r.r; rf (if not
-// null) = r rounded to FP32, the input of the mixed-precision V-cycle
+// alpha = delta / (p.q); x += alpha p; r_old = r; r -= alpha q; partial r.r;
+// rf (if not null) = r rounded to FP32, the input of the mixed-precision V-cycle
 __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                           double* __restrict__ ro,
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q,
                                                            const double* __restrict__ delta,
@@ -139,7 +145,9 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    const double r0 = r[i];
+    ro[i] = r0;
+    const double ri = r0 - alpha * q[i];
     r[i] = ri;
     if (rf) rf[i] = (float)ri;
     s += ri * ri;
@@ -148,18 +156,15 @@ __global__ void __launch_bounds__(VEC_THREADS) k_update_xr(double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// p = z + beta p; r_old = r (z FP64, or the FP32 V-cycle output widened)
+// p = z + beta p (z FP64, or the FP32 V-cycle output widened)
 template <class TZ>
 __global__ void __launch_bounds__(VEC_THREADS) k_update_p(double* __restrict__ p, const TZ* __restrict__ z,
-                                                          const double* __restrict__ r,
-                                                          double* __restrict__ ro,
                                                           const double* __restrict__ beta_p,
                                                           int64_t n, const int* act) {
   if (inactive(act)) return;
   const double beta = beta_p[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     p[i] = (double)z[i] + beta * p[i];
-    ro[i] = r[i];
   }
 }
 
@@ -312,7 +317,7 @@ struct dgmg_handle {
   // PCG (top level, FP64)
   double *pr = nullptr, *pro = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;
   double *part = nullptr, *part2 = nullptr;  // reduction partials
-  double* scal = nullptr;                    // slots: 0 delta, 1 beta, 2 p.q, 3 r.r, 4 z.(r-r_old), 5 z.r
+  double* scal = nullptr;                    // slots: 0 delta, 1 beta, 2 p.q, 3 r.r, 4 z.(r-r_old), 5 z.r, 6 r_old weight
   double* host_scal = nullptr;               // pinned
   // batched use: device flag (kernels return when 0) and the slot receiving r.r
   const int* active = nullptr;
@@ -814,7 +819,7 @@ int precond(dgmg_handle* h, const double* r, double* z, bool widen = true, bool 
 
 // ---------------------------------------------------------------- MGCG phases (Alg. 2)
 // Fixed device scalar slots so that a phase can be captured once and replayed.
-enum { S_DELTA = 0, S_BETA = 1, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5 };
+enum { S_DELTA = 0, S_BETA = 1, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5, S_ROW = 6 };
 
 double* rr_slot(dgmg_handle* h) { return h->rr_out ? h->rr_out : h->scal + S_RR; }
 
@@ -824,7 +829,9 @@ int pcg_init_a(dgmg_handle* h, const double* rhs, const double* x) {
   const int64_t n = h->lv[L].n_dof;
   int rc = k_apply<double>(h, L, 1, x, rhs, h->pr, nullptr, nullptr);
   if (rc) return rc;
-  k_fill_v<double>(h, h->pro, n);
+  // r_old enters with weight 0 until the first direction update (r_old = 0
+  // initially); the first phase a writes it before any read
+  k_fill_v<double>(h, h->scal + S_ROW, 1);
   hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pr, h->pr, n, h->part, h->active);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, rr_slot(h), h->active);
   return check_hip(h, "pcg init");
@@ -841,7 +848,7 @@ int pcg_init_b(dgmg_handle* h) {
   return check_hip(h, "pcg init");
 }
 
-// q = A p; alpha = delta / p.q; x += alpha p; r -= alpha q; r.r
+// q = A p; alpha = delta / p.q; x += alpha p; r_old = r; r -= alpha q; r.r
 int pcg_phase_a(dgmg_handle* h, double* x) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
@@ -850,13 +857,13 @@ int pcg_phase_a(dgmg_handle* h, double* x) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, nb, h->scal + S_PQ, h->active);
   float* rf = mixed(h) ? (float*)h->buf[L].f : nullptr;  // the next V-cycle's FP32 input
-  hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, h->pr, h->pp, h->pq,
+  hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, h->pr, h->pro, h->pp, h->pq,
                      h->scal + S_DELTA, h->scal + S_PQ, n, h->part2, rf, h->active);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part2, RED_BLOCKS, rr_slot(h), h->active);
   return check_hip(h, "pcg phase a");
 }
 
-// z = MG(r); beta = z.(r - r_old) / delta; p = z + beta p; r_old = r; delta = z.r
+// z = MG(r); beta = z.(r - r_old) / delta; p = z + beta p; delta = z.r
 int pcg_phase_b(dgmg_handle* h) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
@@ -868,19 +875,19 @@ int pcg_phase_b(dgmg_handle* h) {
   if (rc) return rc;
   const float* zf = (const float*)h->buf[L].u;
   if (mx)
-    hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, zf, h->pr, h->pro, n,
-                       h->part, h->part2, h->active);
+    hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, zf, h->pr, h->pro,
+                       h->scal + S_ROW, n, h->part, h->part2, h->active);
   else
     hipLaunchKernelGGL((k_dot_zr<double>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pz, h->pr, h->pro,
-                       n, h->part, h->part2, h->active);
+                       h->scal + S_ROW, n, h->part, h->part2, h->active);
   hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, h->part2, RED_BLOCKS,
                      h->scal, h->active);
   if (mx)
-    hipLaunchKernelGGL((k_update_p<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, zf, h->pr, h->pro,
+    hipLaunchKernelGGL((k_update_p<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp, zf,
                        h->scal + S_BETA, n, h->active);
   else
     hipLaunchKernelGGL((k_update_p<double>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pp,
-                       (const double*)h->pz, h->pr, h->pro, h->scal + S_BETA, n, h->active);
+                       (const double*)h->pz, h->scal + S_BETA, n, h->active);
   return check_hip(h, "pcg phase b");
 }
 
