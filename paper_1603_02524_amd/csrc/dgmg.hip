@@ -338,7 +338,8 @@ struct dgmg_handle {
   // variable DGMG_NO_FUSED_RESTRICTION at setup selects the two-step path
   // (same values; kept for comparison)
   bool fuse_restrict = true;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded, not yet read
+  std::vector<hipEvent_t> ev_pool;                       // created once, reused
   std::vector<double> ev_flops, ev_bytes;
   double t_ms = 0, t_flops = 0, t_bytes = 0;
   int64_t t_launch = 0;
@@ -605,6 +606,19 @@ int k_fdm(dgmg_handle* h, int l, int nd, const T* r, int waves) {
 
 // One additive sweep.  u_zero: the caller guarantees u == 0, so the residual
 // f - A u is f itself and the patch solves read f directly.
+// Timing events: taken from a pool created when timing is enabled (no event
+// creation inside a timed region), returned to it once read.
+hipEvent_t take_event(dgmg_handle* h) {
+  if (h->ev_pool.empty()) {
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  hipEvent_t e = h->ev_pool.back();
+  h->ev_pool.pop_back();
+  return e;
+}
+
 template <class T>
 int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero = false) {
   const LevelDev<T>& L = LD<T>(h, l);
@@ -618,8 +632,8 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero =
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = h->timing && l == (int)h->lv.size() - 1;  // top-level launches only
   if (timed) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    e0 = take_event(h);
+    e1 = take_event(h);
     (void)hipEventRecord(e0, h->stream);
   }
   rc = k_fdm<T>(h, l, nd, res, h->waves[l][kind]);
@@ -1359,10 +1373,21 @@ int dgmg_tune_set(dgmg_handle* h, int level, int kind, int waves) {
 int dgmg_kernel_timing(dgmg_handle* h, int enable) {
   if (!h) return DGMG_EINVAL;
   for (auto& e : h->ev) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    h->ev_pool.push_back(e.first);
+    h->ev_pool.push_back(e.second);
   }
   h->ev.clear();
+  if (enable) {
+    // events for a few hundred timed launches, created before any timed region
+    while (h->ev_pool.size() < 1024) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      h->ev_pool.push_back(e);
+    }
+  } else {
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    h->ev_pool.clear();
+  }
   h->ev_flops.clear();
   h->ev_bytes.clear();
   h->t_ms = h->t_flops = h->t_bytes = 0;
@@ -1382,8 +1407,8 @@ int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double
     h->t_flops += h->ev_flops[i];
     h->t_bytes += h->ev_bytes[i];
     h->t_launch += 1;
-    (void)hipEventDestroy(h->ev[i].first);
-    (void)hipEventDestroy(h->ev[i].second);
+    h->ev_pool.push_back(h->ev[i].first);
+    h->ev_pool.push_back(h->ev[i].second);
   }
   h->ev.clear();
   h->ev_flops.clear();
