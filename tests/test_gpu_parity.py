@@ -284,6 +284,35 @@ def test_fused_residual_restriction_is_bitwise_two_step(cid, monkeypatch):
             S2.close()
 
 
+def test_kernel_timing_of_top_level_patch_solves():
+    """dgmg_kernel_timing / dgmg_kernel_time: one event pair per top-level patch
+    solve (FA: 3 sweeps before and 3 after the coarse correction of each of the
+    k V-cycles of a k-iteration solve), algorithmic flops from the tile sizes;
+    a second enable reuses the event pool and starts the counts afresh."""
+    g, m = case("3d_dir_ip_p8_fa")
+    S = D.Solver(g, m)
+    try:
+        n = S.n_dof()
+        f = _dev(np.random.default_rng(24).uniform(-1, 1, n))
+        NA, NL = 2 * m.P, (m.P + 1) + 2 * 2  # face-centred tile 2P x (N_P + 2 N_O), N_O = 2 at P = 8
+        ts = NA * NL * NL
+        per_launch = 4.0 * ts * (NA + 2 * NL) + 2.0 * ts
+        patches = sum(np.prod([g.n[d] + (1 if d == nd else 0) for d in range(3)]) for nd in range(3))
+        for _ in range(2):
+            S.kernel_timing(True)
+            st = S.solve(f, _dev(np.zeros(n)))
+            kt = S.kernel_time()
+            S.kernel_timing(False)
+            k = st["iterations"]
+            assert kt["launches"] == 6 * k
+            assert kt["ms"] > 0
+            assert kt["flops"] == pytest.approx(2 * k * patches * per_launch, rel=1e-12)
+        S.solve(f, _dev(np.zeros(n)))  # timing off: nothing recorded
+        assert S.kernel_time()["launches"] == 0
+    finally:
+        S.close()
+
+
 def test_zero_rhs_and_exact_guess():
     """g = 0 returns at once with x untouched at 0; an initial guess that already
     solves the system to round-off also takes no iteration."""
