@@ -639,9 +639,11 @@ struct NoPost {
 // results of lines past the set are discarded), and stores of rows j >= LEN or
 // of lines past the set go to the lane's slot of `trash` (64 values, dead
 // storage) instead of being masked.
-template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost, int BLEN = (TD == 0 ? NA : NL)>
+template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost, int BLEN = (TD == 0 ? NA : NL),
+          bool TAIL = false>
 __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ trash,
-                                         const BOp<T, BLEN>& B, Post post = Post()) {
+                                         const BOp<T, BLEN>& B, Post post = Post(),
+                                         const T* __restrict__ tail = nullptr) {
   static_assert(BOp<T, BLEN>::KS == BOp<T, TD == 0 ? NA : NL>::KS &&
                     BOp<T, BLEN>::NB == BOp<T, TD == 0 ? NA : NL>::NB,
                 "operand register shape");
@@ -677,7 +679,7 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ t
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[t][nb] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int ks = 0; ks < (TAIL ? KS - 1 : KS); ++ks) {
       const int k = imin(4 * ks + lk, LEN - 1);
       T a[MBLK];
 #pragma unroll
@@ -687,6 +689,22 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ t
         if (act[t])
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) acc[t][nb] = M::op(B.b[nb][ks], a[t], acc[t][nb]);
+    }
+    if constexpr (TAIL) {
+      // LEN = 4 (KS - 1) + 1: the last contraction index is alone in its group
+      // of four, so it is added on the VALU as a rank-one update (tail = row
+      // LEN - 1 of B in LDS) instead of a fourth product that is 3/4 padding
+#pragma unroll
+      for (int t = 0; t < MBLK; ++t) {
+        const T at = act[t] ? tile[base[t] + (LEN - 1) * STRIDE] : T(0);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = imin(nb * 16 + M::row(lk, r), LEN - 1);
+            acc[t][nb][r] = __builtin_fma(tail[j], at, acc[t][nb][r]);
+          }
+      }
     }
 #pragma unroll
     for (int t = 0; t < MBLK; ++t) {
@@ -811,8 +829,15 @@ struct FdmShape {
   }
 };
 
+// Minimum waves per SIMD asked of the compiler: 6 for the 16 x 13 x 13 tile
+// (P = 8 face-centred patches), so that its register use stays within 80 and
+// six 4-wave blocks fit a CU, as its LDS allows; no constraint otherwise.
+template <int NA, int NL>
+constexpr int fdm_min_waves() {
+  return NA == 16 && NL == 13 ? 6 : 1;
+}
 template <class T, int DIM, int NA, int NL, int ND>
-__global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_min_waves<NA, NL>()))) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
                                                   int npx, int npy, int npz) {
   using S = FdmShape<DIM, ND, NA, NL>;
   constexpr int TS = S::TS;
@@ -888,6 +913,16 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
                         NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
                         BOp<T, NA>::NB == BOp<T, NL>::NB;
   BOp<T, NA> P, Q;
+  // lateral lines with NL = 1 (mod 4): the last row of each of their four
+  // matrices in LDS for the rank-one tail of those passes
+  constexpr bool TAILK = PING && NL % 4 == 1;
+  __shared__ T sBt[TAILK ? 4 : 1][TAILK ? NL : 1];
+  if constexpr (TAILK) {
+    const T* rows[4] = {fwd[1], fwd[2], bwd[2], bwd[1]};
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      for (int j = tid; j < NL; j += nth) sBt[m][j] = rows[m][(NL - 1) * NL + j];
+  }
   if constexpr (PING) P.load(fwd[0]);
   if constexpr (PRE) {
     F0.load(fwd[0]);
@@ -966,16 +1001,16 @@ __global__ void __launch_bounds__(512) fdm_kernel(LevelDev<T> L, const T* __rest
     fdm_pass<T, NA, NL, DIM, 0, NoPost, NA>(tile, trash, P);
     __syncthreads();
     P.template load_as<NL>(fwd[2]);
-    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA>(tile, trash, Q);
+    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA, TAILK>(tile, trash, Q, NoPost(), sBt[0]);
     __syncthreads();
     Q.template load_as<NL>(bwd[2]);
-    fdm_pass<T, NA, NL, DIM, 2, decltype(scale), NA>(tile, trash, P, scale);
+    fdm_pass<T, NA, NL, DIM, 2, decltype(scale), NA, TAILK>(tile, trash, P, scale, sBt[1]);
     __syncthreads();
     P.template load_as<NL>(bwd[1]);
-    fdm_pass<T, NA, NL, DIM, 2, NoPost, NA>(tile, trash, Q);
+    fdm_pass<T, NA, NL, DIM, 2, NoPost, NA, TAILK>(tile, trash, Q, NoPost(), sBt[2]);
     __syncthreads();
     Q.template load_as<NA>(bwd[0]);
-    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA>(tile, trash, P);
+    fdm_pass<T, NA, NL, DIM, 1, NoPost, NA, TAILK>(tile, trash, P, NoPost(), sBt[3]);
     __syncthreads();
     fdm_pass<T, NA, NL, DIM, 0, NoPost, NA>(tile, trash, Q);
     __syncthreads();
