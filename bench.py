@@ -45,7 +45,7 @@ HBM_PEAK_GBPS = 8000.0
 # the patch-solve section of kernels.hpp is compared at run time and the
 # figure dropped on any change.
 TRAFFIC = {"bytes_per_launch": 133.7e6,
-           "kernel_src_sha256": "867e3ab0a4888eb000b75ca123d01b4760c6e5ada1a5486185d0b6760c478204",
+           "kernel_src_sha256": "b2a0d70015535f4bc03cf988ae49399c8eb70f813c1603127d39b5c55dc0a2d2",
            "profile": "profiles/fdm_p8_c2_fp64_pmc_traffic.md"}
 KERNEL_SOURCE = "paper_1603_02524_amd/csrc/kernels.hpp"
 KERNEL_SECTION = ("// ================================================================ FDM patch solve",

@@ -913,9 +913,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
                         NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
                         BOp<T, NA>::NB == BOp<T, NL>::NB;
   BOp<T, NA> P, Q;
-  // lateral lines with NL = 1 (mod 4): the last row of each of their four
-  // matrices in LDS for the rank-one tail of those passes
-  constexpr bool TAILK = PING && NL % 4 == 1;
+  // FP64 lateral lines with NL = 1 (mod 4): the last row of each of their
+  // four matrices in LDS for the rank-one tail of those passes (in FP32 the
+  // 16x16x4 product costs half as much and the tail measured slower)
+  constexpr bool TAILK = PING && NL % 4 == 1 && sizeof(T) == 8;
   __shared__ T sBt[TAILK ? 4 : 1][TAILK ? NL : 1];
   if constexpr (TAILK) {
     const T* rows[4] = {fwd[1], fwd[2], bwd[2], bwd[1]};
