@@ -30,6 +30,7 @@ CASES = [
     ("3d_dir_ip_p8_fa", dict(dim=3, n=(2, 3, 2), seed=6), dict(P=8, smoother="FA")),
     ("3d_per_ip_p6_fa", dict(dim=3, n=(3, 3, 3), periodic=True, seed=7), dict(P=6, smoother="FA")),
     ("3d_dir_ip_p8_ea0", dict(dim=3, n=(3, 2, 2), seed=8), dict(P=8, smoother="EA", overlap="zero")),
+    ("3d_dir_ip_p8_ea", dict(dim=3, n=(2, 3, 2), seed=28), dict(P=8, smoother="EA")),
     ("3d_dir_ip_p12_fa", dict(dim=3, n=(2, 2, 1), seed=9), dict(P=12, smoother="FA")),
     ("3d_dir_ip_p16_ea", dict(dim=3, n=(2, 1, 2), seed=10), dict(P=16, smoother="EA")),
     ("3d_dir_ip_p16_fa", dict(dim=3, n=(1, 2, 2), seed=13), dict(P=16, smoother="FA")),
