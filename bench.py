@@ -45,7 +45,7 @@ HBM_PEAK_GBPS = 8000.0
 # the patch-solve section of kernels.hpp is compared at run time and the
 # figure dropped on any change.
 TRAFFIC = {"bytes_per_launch": 133.7e6,
-           "kernel_src_sha256": "b2a0d70015535f4bc03cf988ae49399c8eb70f813c1603127d39b5c55dc0a2d2",
+           "kernel_src_sha256": "dcade7b4b14fe7fab6692c5f761499aa8e5873dff0024b26a2380f6288ca0dd7",
            "profile": "profiles/fdm_p8_c2_fp64_pmc_traffic.md"}
 KERNEL_SOURCE = "paper_1603_02524_amd/csrc/kernels.hpp"
 KERNEL_SECTION = ("// ================================================================ FDM patch solve",

@@ -852,7 +852,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
   // their store trash (64 values)
   __shared__ __align__(8) int rowoff[imax(S::NROW, 64 * (int)sizeof(T) / (int)sizeof(int))];
   __shared__ int rowpos[S::NROW];
-  __shared__ T roww[S::NROW];
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   const int pid = xcd_block(npatch);
   if (pid < 0 || inactive(L.active)) return;
@@ -878,13 +877,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
     }
   }
   // per row (o1, o2) of the grid-natural order: its offset in the level vector
-  // (-1 outside a Dirichlet domain), its tile position and its weight w1 w2
+  // (-1 outside a Dirichlet domain) and its tile position (its weight w1 w2 is
+  // formed from the per-direction tables at the scatter)
   for (int rw = tid; rw < S::NROW; rw += nth) {
     const int o1 = DIM == 3 ? rw % S::L1 : rw, o2 = DIM == 3 ? rw / S::L1 : 0;
     const int g1 = go[1][o1], g2 = DIM == 3 ? go[2][o2] : 0;
     rowoff[rw] = (g1 | g2) < 0 ? -1 : g1 + g2;
     rowpos[rw] = S::tpos(0, o1, o2);
-    roww[rw] = DIM == 3 ? wg[1][o1] * wg[2][o2] : wg[1][o1];
   }
   // 1D matrices of each tile dimension: forward t_j = sum_k S_kj r_k uses S,
   // backward u_k = sum_j S_kj t_j uses S^T (both row-major)
@@ -1037,19 +1036,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
   if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, bwd[0], fwd[0]);
   __syncthreads();
   }
-  // weighted result w_s (.) Delta u_s in grid-natural order
+  // weighted result w_s (.) Delta u_s in grid-natural order; row weight w1 w2
+  const auto row_w = [&](int rw) -> T {
+    if constexpr (DIM == 3) return wv[1][rw % S::L1] * wv[2][rw / S::L1];
+    else return wv[1][rw];
+  };
   T* dst = out + (int64_t)pid * TS;
   if constexpr (G2D) {
     const int o0 = tid & 15, rstep = nth >> 4;
     if (o0 < S::L0) {
       const T w0 = wv[0][o0];
       const int pc = o0 * S::C0;
-      for (int rw = tid >> 4; rw < S::NROW; rw += rstep) dst[rw * S::L0 + o0] = (w0 * roww[rw]) * tile[rowpos[rw] + pc];
+      for (int rw = tid >> 4; rw < S::NROW; rw += rstep) dst[rw * S::L0 + o0] = (w0 * row_w(rw)) * tile[rowpos[rw] + pc];
     }
   } else {
     for (int q = tid; q < TS; q += nth) {
       const int o0 = q % S::L0, rw = q / S::L0;
-      dst[q] = (wv[0][o0] * roww[rw]) * tile[rowpos[rw] + o0 * S::C0];
+      dst[q] = (wv[0][o0] * row_w(rw)) * tile[rowpos[rw] + o0 * S::C0];
     }
   }
 }
