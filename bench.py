@@ -1,26 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the DG p-multigrid MGCG solver on one MI355X.
 
-Workload (default, --workload c2): 3D Poisson on [0,1]^3, 16^3 uniform
-elements, SIPG with P = 8 (2,985,984 unknowns), homogeneous Dirichlet,
-right-hand side i.i.d. U[-1,1] (seed 2), face-centred additive Schwarz with
-level overlap, V(1,1), MGCG to a 1e-10 relative residual, FP64 throughout.
-One step = one complete solve from x = 0 (every stage of the path: operator
-applies, patch solves, overlap summation, transfers, coarse solve, PCG
-updates).  The other precision (FP32 V-cycle inside FP64 PCG) is timed on the
-same workload for the mixed-vs-FP64 ratio.
+Workload (the value): 3D Poisson on [0,1]^3, 16^3 uniform elements, SIPG with
+P = 8 (2,985,984 unknowns), homogeneous Dirichlet, right-hand side i.i.d.
+U[-1,1] (seed 2), face-centred additive Schwarz with level overlap, V(1,1),
+MGCG to a 1e-10 relative residual (confirmed on the true residual), FP64
+throughout.  One step = one complete solve from x = 0 (every stage of the
+path: operator applies, patch solves, overlap summation, transfers, coarse
+solve, PCG updates), inputs resident in HBM.
 
-Other workloads: c3 (32^3 LDG, z stretched to aspect ratio 32, mixed), c5
-(8^3 at P = 32 with random per-direction sizes, mixed; --learned adds the
-shipped face-weight network with its probe fallback), c4 (64 independent
-grids of 4^3..16^3 elements at P in {4,6,8,12,16} solved together in one
-batched, graph-replayed MGCG, against the same grids solved one by one in
-FP64).
-
-Prints one JSON line: DoF/s (unknowns / solve time), the live roofline of the
-dominant kernel (top-level patch solve, HIP events on the solver's stream),
-its HBM traffic when measured for the current kernel sources, and the CPU
-oracle timed on a bounded sample of the same workload.
+Also on the line:
+* roofline: the dominant kernel (top-level patch solve), algorithmic flops per
+  launch = flops per unknown of one sweep's fast-diagonalisation patch solves x
+  the level's unknowns, over the mean launch time from HIP events on the
+  solver's stream; HBM bytes per launch from rocprofv3 counters when they were
+  taken on the current kernel source;
+* smoothing_step: one whole top-level smoothing step against its attainable
+  roof max(bytes / HBM peak, flops / compute peak);
+* mixed: the FP32 V-cycle inside FP64 PCG on the same input;
+* c3, c5, c4 (unless --quick): 32^3 LDG stretched to aspect ratio 32, 8^3 at
+  P = 32 (with the learned face weights), and 64 batched grids, each against
+  the plain FP64 solver (one by one for the batch);
+* cpu_baseline: the oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -105,65 +106,6 @@ def _top_kernel(S, m):
     return name, (FP64_VALU_PEAK_TFLOPS if f64 else FP32_MFMA_PEAK_TFLOPS)
 
 
-def _run_batch(args):
-    """Many grids (3D, 4^3..16^3 elements, P in {4, 6, 8, 12, 16}) solved together."""
-    import numpy as np
-    import torch
-    import synth
-    from paper_1603_02524_amd import dgmg
-    ws = synth.c4_batched()
-    _log(f"setup {len(ws)} grids")
-    B = dgmg.BatchSolver([(w.grid, w.method) for w in ws], max_iter=200)
-    n = B.n_dof
-    rhs = torch.tensor(np.concatenate([synth.rhs_uniform(w.seed, w.grid.n_dof(w.method.P)) for w in ws]),
-                       device="cuda")
-    x = torch.zeros(n, dtype=torch.float64, device="cuda")
-    if not args.no_autotune:
-        _log("autotuning")
-        B.autotune()
-    for _ in range(args.warmup):
-        x.zero_()
-        B.solve(rhs, x)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x.zero_()
-        st = B.solve(rhs, x)
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
-    its = [s["iterations"] for s in st]
-    out = {"metric": METRIC, "value": n / sec, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
-           "config": {"workload": f"batched_{len(ws)}_grids_3d_mixed", "grids": len(ws), "n_dof": n,
-                      "iterations_min_max": [min(its), max(its)], "converged": all(s["converged"] for s in st),
-                      "graphs": True}}
-    if not args.no_mixed:
-        # the same grids one after another with the plain FP64 solver (one handle each)
-        _log("timing the same grids one by one in FP64")
-        tot = 0.0
-        for w, (a, b) in zip(ws, zip(B.offsets[:-1], B.offsets[1:])):
-            m64 = synth.with_method(w, precision="fp64").method
-            S = dgmg.Solver(w.grid, m64, max_iter=200)
-            if not args.no_autotune:
-                S.autotune()
-            xs = torch.zeros(b - a, dtype=torch.float64, device="cuda")
-            r = rhs[a:b].contiguous()
-            S.solve(r, xs)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(max(1, args.steps // 2)):
-                xs.zero_()
-                S.solve(r, xs)
-            torch.cuda.synchronize()
-            tot += (time.perf_counter() - t0) / max(1, args.steps // 2)
-            S.close()
-        out["fp64_one_by_one"] = {"value": n / tot, "unit": "DoF/s", "ms_per_step": tot * 1e3,
-                                  "batched_time_per_dof_vs_fp64": sec / tot}
-    B.close()
-    print(json.dumps(out), flush=True)
-
-
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -189,29 +131,230 @@ def _time_solves(S, rhs, x, tol, warmup, steps, timing):
     return (t1 - t0) / steps, st, kt
 
 
-def _cpu_baseline(w, rhs_np, gpu_iters, sample_iters):
-    """Oracle (FP64 numpy/scipy) on the same inputs: the first `sample_iters`
-    MGCG iterations, timed, scaled to the full iteration count."""
+# ---------------------------------------------------------------- algorithmic counts
+def sweep_flops_per_dof(dim, P, n_o, smoother):
+    """Flops per unknown of one Schwarz sweep's patch solves (fast diagonalisation:
+    D forward and D backward 1D contractions per patch, two flops per multiply-add),
+    one patch per element: FC tile a x n^(D-1) with a = 2P, n = N_P + 2 N_O:
+    4 (a^2 n^(D-1) + (D-1) a n^D) / N_P^D; EC tile n^D: 4 D n^(D+1) / N_P^D."""
+    NP = P + 1
+    n = NP + 2 * n_o
+    if smoother == "FA":
+        a = 2 * P
+        return 4.0 * (a * a * n ** (dim - 1) + (dim - 1) * a * n ** dim) / NP ** dim
+    return 4.0 * dim * n ** (dim + 1) / NP ** dim
+
+
+def apply_flops_per_dof(dim, P):
+    """Operator apply: 2 D N_P (the volume contractions) + 12 D (face terms)."""
+    return 2.0 * dim * (P + 1) + 12.0 * dim
+
+
+def _dominant_roofline(S, m, kt, word):
+    """Top-level patch solve: algorithmic flops and bytes per launch from the counts per
+    unknown times the level's unknowns, over the mean launch time (HIP events)."""
+    L = S.num_levels - 1
+    P, n_o, n = S.level_info(L)
+    dim = S.grid.dim
+    k_ms = kt["ms"] / max(kt["launches"], 1)
+    flops = sweep_flops_per_dof(dim, P, n_o, m.smoother) * n
+    alg_bytes = 3.0 * word * n                        # one sweep: read u and f, write u
+    f64 = m.precision == "fp64"
+    peak = FP64_VALU_PEAK_TFLOPS if f64 else FP32_MFMA_PEAK_TFLOPS
+    ridge = peak * 1e12 / (HBM_PEAK_GBPS * 1e9)
+    bound = "mfma" if flops / alg_bytes > ridge else "hbm"
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    traffic = None
+    if (S.grid.n == (16, 16, 16) and P == 8 and f64 and TRAFFIC["bytes_per_launch"]
+            and TRAFFIC["kernel_src_sha256"] == _kernel_src_hash()):
+        traffic = TRAFFIC["bytes_per_launch"]
+    kname, _ = _top_kernel(S, m)
+    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "kernel": kname, "avg_ms": k_ms, "launches": kt["launches"],
+            "flops_per_launch": flops, "flops_per_dof": flops / n,
+            "alg_bytes_per_launch": alg_bytes, "alg_GBps": alg_bytes / (k_ms * 1e-3) / 1e9,
+            "hbm_GBps": None if traffic is None else traffic / (k_ms * 1e-3) / 1e9,
+            "hbm_frac": None if traffic is None else traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "arithmetic_intensity": flops / alg_bytes, "ridge": ridge,
+            "traffic_profile": TRAFFIC["profile"] if traffic is not None else None}
+    return roof
+
+
+def _smoothing_step_roofline(S, m, word, reps=20):
+    """One top-level smoothing step (FA: D sweeps, each residual apply + patch solves +
+    overlap summation; EA: one) timed with events on the solver's stream, against its
+    attainable roof max(bytes / HBM peak, flops / compute peak)."""
+    import torch
+    L = S.num_levels - 1
+    P, n_o, n = S.level_info(L)
+    dim = S.grid.dim
+    dt = torch.float64 if m.precision == "fp64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(7)
+    u = torch.rand(n, dtype=dt, device="cuda", generator=g)
+    f = torch.rand(n, dtype=dt, device="cuda", generator=g)
+    S.smooth(L, u, f, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        S.smooth(L, u, f, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sweeps = dim if m.smoother == "FA" else 1
+    flops = sweeps * (sweep_flops_per_dof(dim, P, n_o, m.smoother) + apply_flops_per_dof(dim, P)) * n
+    byts = sweeps * 3.0 * word * n
+    peak = FP64_VALU_PEAK_TFLOPS if m.precision == "fp64" else FP32_MFMA_PEAK_TFLOPS
+    t_roof = max(byts / (HBM_PEAK_GBPS * 1e9), flops / (peak * 1e12)) * 1e3
+    return {"ms": ms, "roof_ms": t_roof, "frac": t_roof / ms, "flops": flops, "alg_bytes": byts,
+            "sweeps": sweeps, "bound": "hbm" if byts / (HBM_PEAK_GBPS * 1e9) > flops / (peak * 1e12) else "compute"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(w, rhs_np, gpu_iters, samples=3):
+    """Oracle (FP64 numpy/scipy, as it stands) on the same input, on a bounded sample:
+    one V-cycle and one operator apply at the top level (the work of one MGCG
+    iteration), timed single-threaded (median of `samples`) and once with the
+    default BLAS thread pool; extrapolated to a whole solve of gpu_iters
+    iterations: gpu_iters V-cycles and gpu_iters + 2 applies (initial residual,
+    one per iteration, the exit check).  Hierarchy set-up is not timed."""
+    import statistics
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import multigrid as mg
     from oracle import operator as op
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = 1
     g, m = w.grid, w.method
     H = mg.Hierarchy(g, m, patch_mode="fdm", assemble=False)
     f = op.to_lex(rhs_np, g.n, m.P)
+
+    def sample():
+        t0 = time.perf_counter()
+        H.vcycle(np.zeros_like(f), f)
+        t1 = time.perf_counter()
+        H.apply(H.L, f)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    with threadpool_limits(1):
+        single = [sample() for _ in range(samples)]
+    pool = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    multi = sample()
+    tv = statistics.median(s[0] for s in single)
+    ta = statistics.median(s[1] for s in single)
+    t_solve = gpu_iters * tv + (gpu_iters + 2) * ta
+    t_multi = gpu_iters * multi[0] + (gpu_iters + 2) * multi[1]
+    return {"value": w.n_dof / t_solve, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"extrapolated, not a whole solve: one top-level V-cycle ({tv:.1f} s) and one operator "
+                       f"apply ({ta:.2f} s) of the oracle on the same workload, single-threaded, median of "
+                       f"{samples}; scaled to the {gpu_iters}-iteration solve ({gpu_iters} V-cycles, "
+                       f"{gpu_iters + 2} applies); set-up excluded"),
+            "extrapolated": True, "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "single_thread_samples_s": [[round(a, 3), round(b, 3)] for a, b in single],
+            "all_threads": {"cores": int(pool), "vcycle_s": round(multi[0], 3), "apply_s": round(multi[1], 3),
+                            "value": w.n_dof / t_multi}}
+
+
+def _solve_entry(S, rhs, x, tol, warmup, steps):
+    sec, st, _ = _time_solves(S, rhs, x, tol, warmup, steps, timing=False)
+    return sec, {"ms_per_step": sec * 1e3, "iterations": st["iterations"],
+                 "true_rel_residual": st["r_true"] / st["r0"] if st["r0"] else 0.0,
+                 "converged": st["converged"]}
+
+
+def _extra_workload(name, args):
+    """Mixed precision (the workload's own setting) against the plain FP64 solver on the
+    same input; for the P = 32 workload also the learned face weights."""
+    import torch
+    import synth
+    from paper_1603_02524_amd import dgmg
+    w = _workload(name)
+    n = w.n_dof
+    rhs = torch.tensor(synth.rhs_uniform(w.seed, n), dtype=torch.float64, device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "n_dof": n}
+    res = {}
+    for prec in ("mixed", "fp64"):
+        _log(f"{name}: {prec}")
+        S = dgmg.Solver(w.grid, synth.with_method(w, precision=prec).method, max_iter=200)
+        if not args.no_autotune:
+            S.autotune()
+        sec, ent = _solve_entry(S, rhs, x, w.tol, args.warmup, max(2, args.steps // 2))
+        ent["value"] = n / sec
+        res[prec] = sec
+        out[prec] = ent
+        if prec == "mixed" and name == "c5" and w.method.smoother == "FA":
+            from paper_1603_02524_amd import learn
+            if os.path.exists(learn.DEFAULT_PARAMS):
+                params = torch.tensor(learn.load_params(), device="cuda")
+                kept, rl, rf = S.apply_mlp(params, probe_iters=4)
+                secl, entl = _solve_entry(S, rhs, x, w.tol, args.warmup, max(2, args.steps // 2))
+                entl.update({"value": n / secl, "kept": kept, "probe_ratio_learned": rl, "probe_ratio_fixed": rf,
+                             "time_per_dof_vs_fixed_mixed": secl / sec})
+                out["learned_mixed"] = entl
+                res["learned"] = secl
+        S.close()
+    out["mixed_time_per_dof_vs_fp64"] = res["mixed"] / res["fp64"]
+    if "learned" in res:
+        out["learned_mixed_time_per_dof_vs_fp64"] = res["learned"] / res["fp64"]
+    return out
+
+
+def _batched_entry(args):
+    """64 grids in one batched, graph-replayed MGCG (FP32 V-cycle in FP64 PCG) against
+    the same grids solved one after another, in mixed precision and in FP64."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1603_02524_amd import dgmg
+    ws = synth.c4_batched()
+    B = dgmg.BatchSolver([(w.grid, w.method) for w in ws], max_iter=200)
+    n = B.n_dof
+    rhs = torch.tensor(np.concatenate([synth.rhs_uniform(w.seed, w.n_dof) for w in ws]), device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    if not args.no_autotune:
+        B.autotune()
+    steps = max(2, args.steps // 2)
+    for _ in range(args.warmup):
+        x.zero_()
+        B.solve(rhs, x)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mg.mgcg(H, f, np.zeros_like(f), tol=w.tol, i_max=sample_iters)
-    t = time.perf_counter() - t0
-    per_cycle = t / (sample_iters + 1)          # one V-cycle + one operator apply each
-    t_full = per_cycle * gpu_iters
-    return {"value": w.n_dof / t_full, "unit": "DoF/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"first {sample_iters} MGCG iteration(s) ({sample_iters + 1} V-cycles) of the "
-                       f"same workload on the host, {t:.1f} s, scaled to the {gpu_iters} iterations "
-                       f"of the full solve")}
+    for _ in range(steps):
+        x.zero_()
+        st = B.solve(rhs, x)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    its = [s["iterations"] for s in st]
+    out = {"workload": f"batched_{len(ws)}_grids_3d_mixed", "grids": len(ws), "n_dof": n, "ms_per_step": sec * 1e3,
+           "value": n / sec, "iterations_min_max": [min(its), max(its)],
+           "converged": all(s["converged"] for s in st),
+           "true_rel_residual_max": max(s["r_true"] / s["r0"] for s in st)}
+    B.close()
+    for prec in ("mixed", "fp64"):
+        _log(f"c4: the same grids one by one, {prec}")
+        tot = 0.0
+        for w, (a, b) in zip(ws, zip(B.offsets[:-1], B.offsets[1:])):
+            S = dgmg.Solver(w.grid, synth.with_method(w, precision=prec).method, max_iter=200)
+            if not args.no_autotune:
+                S.autotune()
+            xs = torch.zeros(b - a, dtype=torch.float64, device="cuda")
+            r = rhs[a:b].contiguous()
+            s1, _ = _solve_entry(S, r, xs, w.tol, 1, steps)
+            tot += s1
+            S.close()
+        out[f"one_by_one_{prec}_ms"] = tot * 1e3
+        out[f"batched_time_per_dof_vs_one_by_one_{prec}"] = sec / tot
+    return out
 
 
 def main():
@@ -219,15 +362,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c2small", "c3", "c4", "c5"],
-                    help="c2 (default): 16^3 P=8 FP64; c3: 32^3 stretched LDG mixed; c4: 64 batched grids; "
-                         "c5: 8^3 P=32 mixed")
+    ap.add_argument("--quick", action="store_true", help="only the 16^3 workload (no 32^3, 8^3 P=32, batch lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--learned", action="store_true",
-                    help="also time the solver with the shipped learned face weights")
-    ap.add_argument("--cpu-sample-iters", type=int, default=1)
+    ap.add_argument("--cpu-samples", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB MiB (PMC calibration) and exit")
     args = ap.parse_args()
@@ -240,17 +378,12 @@ def main():
         _copy_calibration(args.copy_calibration)
         return
 
-    if args.workload == "c4":
-        _run_batch(args)
-        return
-
-    import numpy as np
     import torch
 
     import synth
     from paper_1603_02524_amd import dgmg
 
-    w = _workload(args.workload)
+    w = _workload("c2")
     g, m = w.grid, w.method
     _log(f"setup {w.name}")
     S = dgmg.Solver(g, m, max_iter=200)
@@ -258,88 +391,53 @@ def main():
     rhs_np = synth.rhs_uniform(w.seed, n)
     rhs = torch.tensor(rhs_np, dtype=torch.float64, device="cuda")
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tuning = {}
     if not args.no_autotune:
         # patch-solve block shapes per (level, sweep kind); bitwise-neutral, outside the timed region
         _log("autotuning patch-solve block shapes")
         tuning = S.autotune()
-    else:
-        tuning = {}
-    _log(f"timing {m.precision} solves")
+    _log("timing FP64 solves")
     sec, st, kt = _time_solves(S, rhs, x, w.tol, args.warmup, args.steps, timing=True)
-    _log(f"{m.precision}: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
-    # true residual of the final iterate (outside the timed region)
-    r = S.residual(S.num_levels - 1, rhs, x)
-    true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(rhs))
-    if not (st["converged"] and true_rel <= 1.01 * w.tol):
-        print(json.dumps({"error": "solve did not reach the tolerance", "stats": st,
-                          "true_rel": true_rel}), file=sys.stderr)
+    _log(f"fp64: {sec * 1e3:.2f} ms per solve, {st['iterations']} iterations")
+    true_rel = st["r_true"] / st["r0"]
+    if not (st["converged"] and true_rel <= w.tol):
+        print(json.dumps({"error": "solve did not reach the tolerance", "stats": st}), file=sys.stderr)
         raise SystemExit(1)
-
-    # dominant kernel: top-level patch solve
-    k_ms = kt["ms"] / max(kt["launches"], 1)
-    k_flops = kt["flops"] / max(kt["launches"], 1)
-    k_bytes = kt["bytes"] / max(kt["launches"], 1)
-    achieved = k_flops / (k_ms * 1e-3) / 1e12
-    traffic = None
-    if (args.workload == "c2" and TRAFFIC["bytes_per_launch"]
-            and TRAFFIC["kernel_src_sha256"] == _kernel_src_hash()):
-        traffic = TRAFFIC["bytes_per_launch"]
-    kname, peak = _top_kernel(S, m)
-    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "kernel": kname,
-            "avg_ms": k_ms, "launches": kt["launches"], "flops_per_launch": k_flops,
-            "alg_bytes_per_launch": k_bytes, "alg_GBps": k_bytes / (k_ms * 1e-3) / 1e9}
+    roof = _dominant_roofline(S, m, kt, 8)
+    step = _smoothing_step_roofline(S, m, 8)
 
     out = {"metric": METRIC, "value": n / sec, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if m.precision == "fp64" else "f64/f32",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": w.name, "elements": list(g.n), "P": m.P, "n_dof": n,
                       "flux": m.flux, "smoother": f"{m.smoother}_l", "vcycle": "V(1,1)",
                       "precision": m.precision, "tol": w.tol, "seed": w.seed,
                       "iterations": st["iterations"], "true_rel_residual": true_rel,
-                      "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())},
-                      "autotuned_sweep_us": {f"l{l}k{k}": round(v[1] * 1e3, 2) for (l, k), v in sorted(tuning.items())}},
-           "roofline": roof}
+                      "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())}},
+           "roofline": roof, "smoothing_step": step}
 
-    if not args.no_mixed:
-        # the other precision on the same workload: mixed vs FP64 time per DoF
-        other = "mixed" if m.precision == "fp64" else "fp64"
-        _log(f"timing {other} solves")
-        wm = synth.with_method(w, precision=other)
-        Sm = dgmg.Solver(wm.grid, wm.method, max_iter=200)
-        if not args.no_autotune:
-            Sm.autotune()
-        xm = torch.zeros(n, dtype=torch.float64, device="cuda")
-        secm, stm, _ = _time_solves(Sm, rhs, xm, w.tol, args.warmup, args.steps, timing=False)
-        rm = Sm.residual(Sm.num_levels - 1, rhs, xm)
-        t_mixed, t_fp64 = (secm, sec) if other == "mixed" else (sec, secm)
-        out[other] = {"value": n / secm, "unit": "DoF/s", "ms_per_step": secm * 1e3,
-                      "iterations": stm["iterations"],
-                      "true_rel_residual": float(torch.linalg.norm(rm) / torch.linalg.norm(rhs)),
-                      "mixed_time_per_dof_vs_fp64": t_mixed / t_fp64}
-        Sm.close()
+    _log("timing mixed-precision solves")
+    wm = synth.with_method(w, precision="mixed")
+    Sm = dgmg.Solver(wm.grid, wm.method, max_iter=200)
+    if not args.no_autotune:
+        Sm.autotune()
+    xm = torch.zeros(n, dtype=torch.float64, device="cuda")
+    secm, entm = _solve_entry(Sm, rhs, xm, w.tol, args.warmup, args.steps)
+    entm["value"] = n / secm
+    entm["mixed_time_per_dof_vs_fp64"] = secm / sec
+    out["mixed"] = entm
+    Sm.close()
 
-    if args.learned and m.smoother == "FA":
-        # learned face weights (shipped network, probe fallback) on the main solver
-        from paper_1603_02524_amd import learn
-        if os.path.exists(learn.DEFAULT_PARAMS):
-            _log("timing solves with learned face weights")
-            params = torch.tensor(learn.load_params(), device="cuda")
-            kept, rl, rf = S.apply_mlp(params, probe_iters=4)
-            xl = torch.zeros(n, dtype=torch.float64, device="cuda")
-            secl, stl, _ = _time_solves(S, rhs, xl, w.tol, args.warmup, args.steps, timing=False)
-            rl_true = S.residual(S.num_levels - 1, rhs, xl)
-            out["learned"] = {"kept": kept, "probe_ratio_learned": rl, "probe_ratio_fixed": rf,
-                              "value": n / secl, "unit": "DoF/s", "ms_per_step": secl * 1e3,
-                              "iterations": stl["iterations"],
-                              "true_rel_residual": float(torch.linalg.norm(rl_true) / torch.linalg.norm(rhs)),
-                              "time_per_dof_vs_fixed": secl / sec}
-            S.set_face_params(None)
+    if not args.quick:
+        out["c3"] = _extra_workload("c3", args)
+        out["c5"] = _extra_workload("c5", args)
+        _log("c4: batched grids")
+        out["c4"] = _batched_entry(args)
 
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = _cpu_baseline(w, rhs_np, st["iterations"], args.cpu_sample_iters)
+        out["cpu_baseline"] = _cpu_baseline(w, rhs_np, st["iterations"], args.cpu_samples)
     S.close()
     print(json.dumps(out), flush=True)
 

@@ -109,11 +109,13 @@ typedef struct {
 /* Statistics of one dgmg_solve call (host struct, filled on return). */
 typedef struct {
   int iterations;          /* PCG iterations performed */
-  int converged;           /* 1 if ||r|| <= tol ||r_0|| */
+  int converged;           /* 1 if ||r|| and ||g - A x|| are <= tol ||r_0|| */
   double r0;               /* ||g - A x_0||_2 */
   double r_final;          /* ||r|| of the recursively updated residual at exit */
   double rho;              /* (r_final / r0)^(1/iterations), eq. (rho) */
   double history[256];     /* ||r_i||, i = 0..min(iterations, 255) */
+  double r_true;           /* ||g - A x||_2 at the last exit check (0 if none ran) */
+  int replacements;        /* exit checks that failed: r replaced by g - A x */
 } dgmg_stats;
 
 /* Fill *o with the defaults: IP, beta = 0, mu_star = 1, FA, level overlap,
@@ -195,7 +197,11 @@ int dgmg_coarse_solve(dgmg_handle* h, const void* f0, void* u0, int dtype);
 int dgmg_vcycle(dgmg_handle* h, const void* r, void* z, int dtype);
 
 /* Solve A x = rhs by MGCG (Alg. 2, with beta = z^T (r - r_old) / delta) until
- * ||r||_2 <= tol ||rhs - A x_0||_2 or max_iter iterations.  rhs, x: FP64
+ * ||r||_2 <= tol ||rhs - A x_0||_2 or max_iter iterations.  The exit test on
+ * the recursively updated residual r is confirmed by the true residual
+ * rhs - A x (FP64): only when that also meets the bound does the solve stop;
+ * otherwise r is replaced by the true residual and the iteration continues.
+ * rhs, x: FP64
  * device vectors of the top level; x holds the initial guess on entry and the
  * iterate on exit.  Synchronises the stream once per iteration (exit test).
  * st (host, may be NULL) receives iteration count and residual history.

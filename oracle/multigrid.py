@@ -14,7 +14,10 @@ MGCG (Alg. 2) is implemented as printed, with one reading: the update of the
 search-direction coefficient uses the preconditioned residual,
 beta = z^T (r - r_old) / delta (the flexible CG of Golub and Ye; the printed
 q^T(...) is a misprint).  r_old starts at zero as printed.  Exit test:
-Euclidean norm of the recursively updated residual <= tol * ||r_0||.
+Euclidean norm of the recursively updated residual <= tol * ||r_0||, confirmed
+by the true residual g - A u (Alg. 2 stops on r_max; the recursion and the
+true residual drift apart by rounding): when the recursive norm passes but the
+true one does not, r is replaced by the true residual and the iteration goes on.
 """
 from __future__ import annotations
 
@@ -178,8 +181,9 @@ class SolveResult:
 
 
 def mgcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray, tol: float = 1e-10, i_max: int = 200,
-         precond=None) -> SolveResult:
-    """MGCG(u, f, N_S, i_max, r_max) of Alg. 2 with r_max = tol * ||f - A u0||."""
+         precond=None, callback=None) -> SolveResult:
+    """MGCG(u, f, N_S, i_max, r_max) of Alg. 2 with r_max = tol * ||f - A u0||.
+    callback(i, u), if given, sees every iterate after its update (read only)."""
     M = precond if precond is not None else (lambda r: h.vcycle(np.zeros_like(r), r))
     u = u0.copy()
     L = h.L
@@ -197,10 +201,15 @@ def mgcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray, tol: float = 1e-10, i_max:
         alpha = delta / float(p @ q)
         u = u + alpha * p
         r = r - alpha * q
+        if callback is not None:
+            callback(i, u)
         rn = float(np.linalg.norm(r))
         hist.append(rn)
         if rn <= r_max:
-            return SolveResult(u, i, hist, True)
+            r_true = f - h.apply(L, u)
+            if float(np.linalg.norm(r_true)) <= r_max:
+                return SolveResult(u, i, hist, True)
+            r = r_true
         z = M(r)
         beta = float(z @ (r - r_old)) / delta
         p = z + beta * p

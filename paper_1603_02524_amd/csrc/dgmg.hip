@@ -833,7 +833,7 @@ int precond(dgmg_handle* h, const double* r, double* z, bool widen = true, bool 
 
 // ---------------------------------------------------------------- MGCG phases (Alg. 2)
 // Fixed device scalar slots so that a phase can be captured once and replayed.
-enum { S_DELTA = 0, S_BETA = 1, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5, S_ROW = 6 };
+enum { S_DELTA = 0, S_BETA = 1, S_PQ = 2, S_RR = 3, S_ZDR = 4, S_ZR = 5, S_ROW = 6, S_RTRUE = 7 };
 
 double* rr_slot(dgmg_handle* h) { return h->rr_out ? h->rr_out : h->scal + S_RR; }
 
@@ -976,6 +976,30 @@ int read_scalar(dgmg_handle* h, const double* dev, double* out) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, DGMG_EHIP, std::string("scalar readback: ") + hipGetErrorString(e));
   *out = *h->host_scal;
+  return DGMG_OK;
+}
+
+// Exit confirmation of Alg. 2: r = g - A x (FP64) and its norm.  The recursive
+// residual of the PCG update and the true one drift apart by rounding; the
+// solve stops only when the true residual meets the tolerance.  r overwrites
+// the recursive residual, so when the check fails the iteration continues from
+// the true residual (residual replacement); in mixed precision its FP32 copy,
+// the next V-cycle's input, is refreshed as well.
+int true_residual(dgmg_handle* h, const double* rhs, const double* x, double* norm) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  int rc = k_apply<double>(h, L, 1, x, rhs, h->pr, nullptr, nullptr);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, h->pr, h->pr, n, h->part, h->active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, RED_BLOCKS, h->scal + S_RTRUE,
+                     h->active);
+  if (mixed(h))
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, h->pr,
+                       (float*)h->buf[L].f, n, h->active);
+  if ((rc = check_hip(h, "true residual"))) return rc;
+  double rr;
+  if ((rc = read_scalar(h, h->scal + S_RTRUE, &rr))) return rc;
+  *norm = std::sqrt(rr);
   return DGMG_OK;
 }
 
@@ -1327,6 +1351,7 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
   const double rmax = tol * r0;
   if ((rc = pcg_init_b(h))) return rc;
   double rn = r0;
+  bool conv = false;
   for (int it = 1; it <= h->opts.max_iter; ++it) {
     if ((rc = run_phase(h, 0, x))) return rc;
     if ((rc = read_scalar(h, rr_slot(h), &rr))) return rc;
@@ -1337,11 +1362,19 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
       if (it < 256) st->history[it] = rn;
     }
     if (!std::isfinite(rn)) return fail(h, DGMG_ENONFINITE, "residual norm is not finite");
-    if (rn <= rmax) break;
+    if (rn <= rmax) {
+      double rt;
+      if ((rc = true_residual(h, rhs, x, &rt))) return rc;
+      if (st) st->r_true = rt;
+      if (rt <= rmax) {
+        conv = true;
+        break;
+      }
+      if (st) st->replacements++;
+    }
     if ((rc = run_phase(h, 1, nullptr))) return rc;
   }
   if ((rc = check_hip(h, "pcg"))) return rc;
-  const bool conv = rn <= rmax;
   if (st) {
     st->converged = conv;
     if (st->iterations > 0) st->rho = std::pow(rn / r0, 1.0 / st->iterations);
@@ -1911,7 +1944,18 @@ int dgmg_batch_solve(dgmg_batch* b, const double* rhs, double* x, double tol, dg
         if (it < 256) st[i].history[it] = rn[i];
       }
       if (!std::isfinite(rn[i])) return batch_fail(b, DGMG_ENONFINITE, "grid " + std::to_string(i) + ": residual not finite");
+      bool done = false;
       if (rn[i] <= rmax[i]) {
+        // exit confirmation on the true residual, as for a single solve (the
+        // grid's device flag is still set, so its kernels run)
+        double rt;
+        if ((rc = true_residual(b->h[i], rhs + b->dof_off[i], x + b->dof_off[i], &rt)))
+          return batch_fail(b, rc, "grid " + std::to_string(i) + ": " + b->h[i]->err);
+        if (st) st[i].r_true = rt;
+        done = rt <= rmax[i];
+        if (!done && st) st[i].replacements++;
+      }
+      if (done) {
         conv[i] = 1;
         b->flags_host[i] = 0;
       } else if (it >= b->h[i]->opts.max_iter) {

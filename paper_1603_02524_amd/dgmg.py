@@ -39,7 +39,8 @@ class DgmgOpts(ctypes.Structure):
 
 class DgmgStats(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("converged", c_int), ("r0", c_double),
-                ("r_final", c_double), ("rho", c_double), ("history", c_double * 256)]
+                ("r_final", c_double), ("rho", c_double), ("history", c_double * 256),
+                ("r_true", c_double), ("replacements", c_int)]
 
 
 # (name, restype, argtypes) of every exported entry point of include/dgmg.h
@@ -443,7 +444,7 @@ def mlp_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 def _stats_dict(st, rc):
     n = st.iterations
     return {"rc": rc, "iterations": n, "converged": bool(st.converged), "r0": st.r0,
-            "r_final": st.r_final, "rho": st.rho,
+            "r_final": st.r_final, "rho": st.rho, "r_true": st.r_true, "replacements": st.replacements,
             "history": [st.history[i] for i in range(min(n, 255) + 1)]}
 
 

@@ -16,8 +16,12 @@ the GPU solution measured with the oracle's operator.
 Tolerances: FP64 operator and transfers 1e-12 relative (a few ulps of sums of
 O(N_P) terms); the sweep 1e-10 relative to the largest correction (patch
 eigenbases from different eigen-solvers agree to ~1e-13, amplified by the
-patch condition number); the solve's true residual 2e-10 of ||f|| (the solver
-stops on the recursively updated residual at 1e-10)."""
+patch condition number); the solve's true residual 1e-10 ||f|| plus the
+rounding of evaluating f - A x (|f| + |A||x| scaled by gamma_m, with |A||x|
+bounded by the Kronecker sum of the absolute 1D operators); the FP64 iterate
+of the 16^3 solve 1e-10 relative against the oracle's recorded MGCG run
+(tests/golden/make_c2_reference.py: iteration count, residual history and the
+iterate at 4096 sampled positions)."""
 import numpy as np
 import pytest
 
@@ -106,8 +110,25 @@ def test_fullsize_sweep_at_sampled_nodes(big):
     assert err < 1e-10
 
 
+def _residual_bound(H, g, m, fl, xl, tol=1e-10):
+    """tol ||f|| + 2 gamma_m || |f| + |A| |x| || (the rounding of evaluating f - A x
+    in FP64 twice, by the library's exit check and here), with |A| |x| bounded by
+    the Kronecker sum of the element-wise absolute 1D operators (the masses are
+    positive) and m the most terms in a row: the sum over directions of the most
+    non-zeros in a row of the 1D operator."""
+    from oracle.operator import apply_kron
+    ops = [(M, np.abs(Ld)) for (M, Ld) in H.levels[H.L].ops]
+    ax = apply_kron(g, m.P, np.abs(xl), ops=ops)
+    nterms = sum(int((np.asarray(Ld) != 0).sum(axis=1).max()) for (_, Ld) in ops)
+    u = np.finfo(np.float64).eps / 2
+    gam = nterms * u / (1 - nterms * u)
+    return tol * np.linalg.norm(fl) + 2 * gam * np.linalg.norm(np.abs(fl) + ax)
+
+
 def test_fullsize_solve_true_residual(big):
-    """The solve as the bench runs it reaches ||f - A x|| <= 2e-10 ||f|| with the oracle's A."""
+    """The solve as the bench runs it reaches ||f - A x|| <= 1e-10 ||f|| with the
+    oracle's A, up to the rounding of evaluating the residual; the library's own
+    FP64 exit check saw it at or below 1e-10."""
     name, w, S, H = big
     g, m = w.grid, w.method
     n = g.n_dof(m.P)
@@ -116,9 +137,48 @@ def test_fullsize_solve_true_residual(big):
     st = S.solve(_dev(f), x, tol=1e-10)
     xl = to_lex(_host(x), g, m.P)
     fl = to_lex(f, g, m.P)
-    res = np.linalg.norm(fl - H.apply(H.L, xl)) / np.linalg.norm(fl)
-    print(f"  {name}: {st['iterations']} iterations, rho {st['rho']:.4f}, true residual {res:.2e}")
-    assert st["converged"] and res < 2e-10
+    res = np.linalg.norm(fl - H.apply(H.L, xl))
+    bound = _residual_bound(H, g, m, fl, xl)
+    nf = np.linalg.norm(fl)
+    print(f"  {name}: {st['iterations']} iterations, rho {st['rho']:.4f}, true residual {res / nf:.3e} "
+          f"(bound {bound / nf:.4e}), library {st['r_true'] / st['r0']:.3e}")
+    assert st["converged"] and st["r_true"] <= 1e-10 * st["r0"]
+    assert res <= bound
+
+
+def test_fullsize_fp64_solve_matches_oracle_mgcg():
+    """16^3 at P = 8, FP64: the library's MGCG against the oracle's recorded run on the
+    same input -- the same iteration count, the residual history within 1e-6, and
+    the iterate within 1e-10 (relative to the largest sampled entry) at 4096
+    sampled positions, its 2-norm within 1e-10."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_mgcg.json")
+    with open(path) as fh:
+        ref = json.load(fh)
+    w = synth.c2_poisson3d_p8()
+    g, m = w.grid, w.method
+    n = g.n_dof(m.P)
+    assert ref["n_dof"] == n and ref["workload"] == w.name
+    S = D.Solver(g, m, max_iter=200)
+    try:
+        f = _dev(synth.rhs_uniform(w.seed, n))
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st = S.solve(f, x, tol=ref["tol"])
+        k = st["iterations"]
+        print(f"  16^3 fp64: {k} iterations (oracle {ref['iterations']})", flush=True)
+        assert st["converged"] and k == ref["iterations"]
+        assert np.allclose(st["history"], ref["history"], rtol=1e-6, atol=0)
+        it = ref["iterates"][str(k)]
+        idx = np.asarray(ref["sample_index_elem"])
+        xs = _host(x)
+        xr = np.asarray(it["x"])
+        err = np.abs(xs[idx] - xr).max() / np.abs(xr).max()
+        nerr = abs(np.linalg.norm(xs) - it["norm"]) / it["norm"]
+        print(f"  16^3 fp64 iterate: sampled rel err {err:.2e}, norm rel err {nerr:.2e}")
+        assert err <= 1e-10 and nerr <= 1e-10
+    finally:
+        S.close()
 
 
 def test_fullsize_learned_weights_no_worse(big):
@@ -141,9 +201,10 @@ def test_fullsize_learned_weights_no_worse(big):
     st = S.solve(f, x, tol=1e-10)
     xl = to_lex(_host(x), g, m.P)
     fl = to_lex(_host(f), g, m.P)
-    res = np.linalg.norm(fl - H.apply(H.L, xl)) / np.linalg.norm(fl)
+    res = np.linalg.norm(fl - H.apply(H.L, xl))
+    bound = _residual_bound(H, g, m, fl, xl)
     S.set_face_params(None)
     print(f"  {name} learned kept={kept} probe {rl:.3e} vs {rf:.3e}: {st['iterations']} vs {fixed['iterations']} "
-          f"iterations, rho {st['rho']:.4f} vs {fixed['rho']:.4f}, true residual {res:.2e}")
-    assert st["converged"] and res < 2e-10
+          f"iterations, rho {st['rho']:.4f} vs {fixed['rho']:.4f}, true residual {res / np.linalg.norm(fl):.2e}")
+    assert st["converged"] and res <= bound
     assert st["iterations"] <= fixed["iterations"]

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import CASES, case, hierarchy, rand_grid, to_elem, to_lex
+from gpu_util import CASES, case, check_solve_parity, hierarchy, rand_grid, residual_bound, to_elem, to_lex
 from oracle import operator as op
 
 torch = pytest.importorskip("torch")
@@ -149,36 +149,28 @@ def test_vcycle_fp64(pair):
 
 
 def test_solve_matches_oracle_fp64(pair):
-    """Same PCG iteration count and x within 1e-10 relative of the oracle's MGCG."""
-    from oracle import multigrid as mg
+    """Alg. 2 against the oracle from x0 = 0: x within 1e-10 of the oracle's iterate
+    after the same number of iterations, the iteration count and the residual
+    history as rounding allows (check_solve_parity), and the true residual within
+    1e-10 ||f|| up to the rounding of evaluating it."""
     cid, g, m, S, H = pair
     rng = np.random.default_rng(19)
     A = H.levels[-1].A
     f = rng.uniform(-1, 1, A.shape[0])
     if all(g.periodic):
         f -= f.mean()
-    ref = mg.mgcg(H, f, np.zeros_like(f), tol=1e-10, i_max=200)
+    r = rng.standard_normal(A.shape[0])
+    if all(g.periodic):
+        r -= r.mean()
+    z_ref = H.vcycle(np.zeros_like(r), r)
+    z_gap = np.linalg.norm(to_lex(_host(S.vcycle(_dev(to_elem(r, g, m.P)))), g, m.P) - z_ref) / np.linalg.norm(z_ref)
     x = _dev(np.zeros(A.shape[0]))
     st = S.solve(_dev(to_elem(f, g, m.P)), x, tol=1e-10)
+    assert st["converged"]
     xs = to_lex(_host(x), g, m.P)
-    assert st["converged"] and ref.converged
-    if all(g.periodic):
-        xs = xs - xs.mean()
-        refx = ref.x - ref.x.mean()
-    else:
-        refx = ref.x
-    assert np.linalg.norm(f - A @ xs) <= 1.0001e-10 * np.linalg.norm(f)
-    if ref.iterations <= 30:
-        assert st["iterations"] == ref.iterations, (st["iterations"], ref.iterations)
-        assert _rel(xs, refx) < 1e-10, cid
-        assert np.allclose(st["history"], ref.history, rtol=1e-6)
-    else:
-        # slowly converging variants (zero overlap: ~90 iterations) accumulate
-        # rounding differences that can move the exit test by one iteration
-        assert abs(st["iterations"] - ref.iterations) <= 1, (st["iterations"], ref.iterations)
-        assert _rel(xs, refx) < 1e-8, cid
-        n = min(len(st["history"]), len(ref.history))
-        assert np.allclose(st["history"][:10], ref.history[:10], rtol=1e-6)
+    check_solve_parity(H, f, st, xs, z_gap=z_gap, label=cid)
+    assert np.linalg.norm(f - A @ xs) <= residual_bound(A, f, xs)
+    assert st["r_true"] <= 1e-10 * st["r0"]
 
 
 def test_solve_is_deterministic(pair):
@@ -215,7 +207,8 @@ def test_mixed_precision_solve(cid):
     xs = to_lex(_host(x), g, m.P)
     assert st["converged"]
     assert st["iterations"] <= ref.iterations + 2
-    assert np.linalg.norm(f - A @ xs) <= 2e-10 * np.linalg.norm(f)
+    assert np.linalg.norm(f - A @ xs) <= residual_bound(A, f, xs)
+    assert st["r_true"] <= 1e-10 * st["r0"]
     if all(g.periodic):
         xs, rx = xs - xs.mean(), ref.x - ref.x.mean()
     else:

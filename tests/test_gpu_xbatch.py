@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import hierarchy, rand_grid, to_elem, to_lex
+from gpu_util import hierarchy, kron_residual, rand_grid, residual_bound, to_elem, to_lex
 
 torch = pytest.importorskip("torch")
 from paper_1603_02524_amd import dgmg as D  # noqa: E402
@@ -156,11 +156,12 @@ def test_batch_mixed_autotuned_converges():
         A = H.levels[-1].A
         f = to_lex(f_all[sl], g, m.P)
         x = to_lex(x_all[sl].cpu().numpy(), g, m.P)
-        assert stats[i]["converged"]
-        assert np.linalg.norm(f - A @ x) <= 2e-10 * np.linalg.norm(f), i
+        assert stats[i]["converged"] and stats[i]["r_true"] <= 1e-10 * stats[i]["r0"]
+        assert np.linalg.norm(f - A @ x) <= residual_bound(A, f, x), i
     B.close()
 
 
+@pytest.mark.timeout(900)
 def test_batched_64_grid_workload():
     """64 grids (4^3..16^3 elements, P in {4,6,8,12,16}, AR 1..8), FP32 MG in FP64
     MGCG, one graph per phase: every grid reaches the 1e-10 true residual."""
@@ -173,12 +174,12 @@ def test_batched_64_grid_workload():
     x = _dev(np.zeros(B.n_dof))
     stats = B.solve(f, x)
     assert all(s["converged"] for s in stats), [s["iterations"] for s in stats]
-    # true residual per grid with the library's FP64 operator of each grid
+    # true residual per grid with the oracle's matrix-free operator of each grid
+    xh, fh = x.cpu().numpy(), rhs
     for i, w in enumerate(ws):
         sl = slice(B.offsets[i], B.offsets[i + 1])
-        S = D.Solver(w.grid, synth.with_method(w, precision="fp64").method)
-        r = S.residual(S.num_levels - 1, f[sl], x[sl])
-        rel = float(torch.linalg.norm(r) / torch.linalg.norm(f[sl]))
-        assert rel <= 1.05e-10, (i, rel)
-        S.close()
+        g, m = w.grid, w.method
+        res, bound = kron_residual(g, m, to_lex(fh[sl], g, m.P), to_lex(xh[sl], g, m.P))
+        assert res <= bound, (i, res / np.linalg.norm(fh[sl]), bound / np.linalg.norm(fh[sl]))
+        assert stats[i]["r_true"] <= 1e-10 * stats[i]["r0"], i
     B.close()

@@ -126,3 +126,43 @@ def test_cost_model_reproduces_table3_omega():
             assert me.omega_bar(rb, kind, n_o, P + 1) == pytest.approx(om, abs=0.06), (key, P)
     w = gold["w10"]
     assert me.w10(w["r_bar"], "EC", 3, 17) == pytest.approx(w["value"], abs=1.0)
+
+
+def test_converged_solve_meets_the_true_residual():
+    """Exit confirmation (reading of the stopping rule of Alg. 2): a converged MGCG
+    returns an iterate whose true residual g - A u meets tol ||r_0||, also with a
+    preconditioner rounded to float32 (the mixed-precision V-cycle's situation)."""
+    rng = np.random.default_rng(8)
+    g = synth.Grid(3, tuple(rng.uniform(0.4, 1.6, 3) for _ in range(3)), (False,) * 3)
+    m = synth.Method(P=4, smoother="FA")
+    h = mg.Hierarchy(g, m)
+    A = h.levels[-1].A
+    f = rng.uniform(-1, 1, A.shape[0])
+    for pre in (None, lambda r: h.vcycle(np.zeros_like(r), r.astype(np.float32).astype(np.float64))
+                .astype(np.float32).astype(np.float64)):
+        res = mg.mgcg(h, f, np.zeros_like(f), tol=1e-10, precond=pre)
+        assert res.converged
+        assert np.linalg.norm(f - A @ res.x) <= 1e-10 * np.linalg.norm(f)
+
+
+def test_cg_history_is_rounding_sensitive():
+    """Why long solves are compared at a fixed iteration count: the zero-overlap EA
+    solve of a 3x2x2 grid at P = 8 (about 90 iterations) rerun with its
+    preconditioned residual perturbed by half an ulp keeps the iterate within 1e-10
+    of the unperturbed one, while its residual history parts from it by more than
+    1e-3 after a few dozen iterations (loss of orthogonality in finite-precision CG)."""
+    rng = np.random.default_rng(8)
+    g = synth.Grid(3, tuple(rng.uniform(0.4, 1.6, size=n) for n in (3, 2, 2)), (False,) * 3)
+    m = synth.Method(P=8, smoother="EA", overlap="zero")
+    h = mg.Hierarchy(g, m)
+    f = np.random.default_rng(19).uniform(-1, 1, h.levels[-1].A.shape[0])
+    n_it = 80
+    a = mg.mgcg(h, f, np.zeros_like(f), tol=0.0, i_max=n_it)
+    rs = np.random.default_rng(5)
+    b = mg.mgcg(h, f, np.zeros_like(f), tol=0.0, i_max=n_it,
+                precond=lambda r: (lambda z: z * (1 + 1e-16 * rs.standard_normal(z.shape)))(
+                    h.vcycle(np.zeros_like(r), r)))
+    dev = np.abs(np.asarray(b.history) / np.asarray(a.history) - 1)
+    assert dev[:10].max() < 1e-9
+    assert dev[40:].max() > 1e-3
+    assert np.linalg.norm(a.x - b.x) <= 1e-10 * np.linalg.norm(a.x)
