@@ -348,6 +348,21 @@ int dgmg_mlp_backward(const float* params, const float* X, const float* T, int B
 int dgmg_mlp_adam(float* params, const float* grad, float* m, float* v, int n, int t, float lr, float b1,
                   float b2, float eps, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as dgmg_mlp_forward, without the work argument.  The hidden
+ * activations go to a static device array of the library holding
+ * DGMG_MLP_NOALLOC_MAX_ROWS rows (4 MiB, one copy per GPU, kept until the
+ * process ends); its device address is looked up on the first call on each
+ * device, with that device current.  The call allocates nothing.  B above
+ * DGMG_MLP_NOALLOC_MAX_ROWS is rejected with DGMG_EINVAL (message in
+ * dgmg_last_error(NULL)); B = 0 does nothing.  stream must belong to the
+ * current device.  All calls on one GPU share the array (nothing in it needs
+ * to start at zero: every call writes the rows it reads), so calls that
+ * overlap on one GPU, on different streams or host threads, race. */
+#define DGMG_MLP_NOALLOC_MAX_ROWS 8192
+int dgmg_mlp_forward_noalloc(const float* params, const float* X, int B, float* Y, void* stream);
+
 /* Device work bytes needed by dgmg_apply_mlp on this handle. */
 int dgmg_mlp_work_bytes(const dgmg_handle* h, size_t* bytes);
 /* Learned weights with fallback: evaluate the MLP (device params) on the

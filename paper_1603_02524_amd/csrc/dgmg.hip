@@ -28,6 +28,14 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+}  // namespace
+
+// Message for dgmg_last_error(NULL) from the handle-free entry points of other
+// translation units (the MLP kernels).
+void dgmg_set_global_error(const std::string& msg) { g_setup_error = msg; }
+
+namespace {
+
 constexpr int RED_BLOCKS = 1024;  // fixed partial count of the vector reductions
 constexpr int VEC_THREADS = 256;
 

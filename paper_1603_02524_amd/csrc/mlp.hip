@@ -7,8 +7,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "../../include/dgmg.h"
+
+void dgmg_set_global_error(const std::string& msg);
 
 namespace {
 
@@ -110,6 +114,45 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ p, const f
 
 int launch_status() { return hipGetLastError() == hipSuccess ? DGMG_OK : DGMG_EHIP; }
 
+// Work area of dgmg_mlp_forward_noalloc: the hidden activations h1, h2 of up to
+// DGMG_MLP_NOALLOC_MAX_ROWS samples (4 MiB).  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name is
+// only a stand-in: kernels receive the device address looked up once per device
+// with hipGetSymbolAddress (mlp_fwd_scratch_ptr below).
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) float mlp_fwd_scratch[(size_t)DGMG_MLP_NOALLOC_MAX_ROWS * 2 * HID];
+
+std::mutex g_scratch_mu;
+float* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of this device's mlp_fwd_scratch, looked up with the device
+// current on its first use and kept per device.
+int mlp_fwd_scratch_ptr(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    dgmg_set_global_error(std::string("mlp_forward_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+    return DGMG_EHIP;
+  }
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    dgmg_set_global_error("mlp_forward_noalloc: device index beyond the supported 64");
+    return DGMG_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(mlp_fwd_scratch));
+    if (e != hipSuccess || !p) {
+      dgmg_set_global_error(std::string("mlp_forward_noalloc: hipGetSymbolAddress: ") +
+                            (e != hipSuccess ? hipGetErrorString(e) : "null address"));
+      return DGMG_EHIP;
+    }
+    g_scratch_dev[dev] = (float*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return DGMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -119,6 +162,24 @@ int dgmg_mlp_param_count(void) { return NPAR; }
 int dgmg_mlp_forward(const float* params, const float* X, int B, float* Y, float* work, void* stream) {
   if (!params || !X || !Y || !work || B < 0) return DGMG_EINVAL;
   if (B == 0) return DGMG_OK;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(B), dim3(HID), 0, (hipStream_t)stream, params, X, B, Y, work);
+  return launch_status();
+}
+
+int dgmg_mlp_forward_noalloc(const float* params, const float* X, int B, float* Y, void* stream) {
+  if (!params || !X || !Y || B < 0) {
+    dgmg_set_global_error("mlp_forward_noalloc: null pointer or negative row count");
+    return DGMG_EINVAL;
+  }
+  if (B > DGMG_MLP_NOALLOC_MAX_ROWS) {
+    dgmg_set_global_error("mlp_forward_noalloc: " + std::to_string(B) + " rows exceed the maximum of " +
+                          std::to_string(DGMG_MLP_NOALLOC_MAX_ROWS) + " (use dgmg_mlp_forward with a work buffer)");
+    return DGMG_EINVAL;
+  }
+  if (B == 0) return DGMG_OK;
+  float* work = nullptr;
+  int rc = mlp_fwd_scratch_ptr(&work);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_mlp_forward, dim3(B), dim3(HID), 0, (hipStream_t)stream, params, X, B, Y, work);
   return launch_status();
 }

@@ -78,6 +78,7 @@ SIGNATURES = [
     ("dgmg_get_face_params", c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
     ("dgmg_mlp_param_count", c_int, []),
     ("dgmg_mlp_forward", c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    ("dgmg_mlp_forward_noalloc", c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     ("dgmg_mlp_backward", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p]),
     ("dgmg_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, ctypes.c_float,
@@ -388,6 +389,7 @@ def face_features(grid, method):
 
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 6, 64, 2
+MLP_NOALLOC_MAX_ROWS = 8192
 
 
 def mlp_param_count():
@@ -416,6 +418,20 @@ def mlp_forward(params, X):
     if rc:
         raise DgmgError(rc, "mlp forward")
     return Y, work
+
+
+def mlp_forward_noalloc(params, X, Y=None):
+    """Y = MLP(X) with the library's static work area (no device allocation by the
+    library; X rows <= MLP_NOALLOC_MAX_ROWS)."""
+    import torch
+    lib = load_library()
+    B = X.shape[0]
+    if Y is None:
+        Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=X.device)
+    rc = lib.dgmg_mlp_forward_noalloc(_dptr(params), _dptr(X), B, _dptr(Y), _stream(X))
+    if rc:
+        raise DgmgError(rc, lib.dgmg_last_error(None).decode())
+    return Y
 
 
 def mlp_backward(params, X, T, Y, work):
