@@ -64,6 +64,13 @@ extern "C" {
 
 #define DGMG_SMOOTHER_EA 0 /* element-centred weighted additive Schwarz */
 #define DGMG_SMOOTHER_FA 1 /* face-centred weighted additive Schwarz */
+#define DGMG_SMOOTHER_EM 2 /* element-centred multiplicative Schwarz */
+#define DGMG_SMOOTHER_FM 3 /* face-centred multiplicative Schwarz */
+
+/* Subdomain order of the multiplicative smoothers (Sec. 3.1): */
+#define DGMG_ORDER_LEX 0    /* one after another, lexicographic (direction 1 fastest) */
+#define DGMG_ORDER_COLOUR 1 /* colour classes of subdomains that share no node and no
+                               matrix entry, each class solved at once */
 
 #define DGMG_OVERLAP_LEVEL (-1)       /* N_O = 1 + round(P_l / 8) on each level */
 #define DGMG_OVERLAP_LEVEL_FLOOR (-2) /* N_O = 1 + floor(P_l / 8) as printed */
@@ -104,6 +111,7 @@ typedef struct {
   int ns_post;       /* post-smoothing steps N_S2 (>= 0) */
   int precision;     /* DGMG_PREC_* */
   int max_iter;      /* i_max of Alg. 2 */
+  int order;         /* DGMG_ORDER_* (multiplicative smoothers; ignored otherwise) */
 } dgmg_opts;
 
 /* Statistics of one dgmg_solve call (host struct, filled on return). */
@@ -168,15 +176,27 @@ int dgmg_residual(dgmg_handle* h, int level, const void* f, const void* x, void*
  * additive sweep over all element-centred subdomains per step; FA = one sweep
  * per orientation d = 1..D in sequence, the residual recomputed before each
  * (eq. (correction:global), eq. (weight function:ec), eq. (weight
- * function:fc)).  u is updated in place; f unchanged. */
+ * function:fc)).  EM / FM (multiplicative, Sec. 3.1): the subdomains of a
+ * partition one after another (DGMG_ORDER_LEX) or colour class by colour
+ * class (DGMG_ORDER_COLOUR), each on the residual left by the previous ones,
+ * u += R_s^T A_ss^{-1} R_s (f - A u) unweighted; FM sweeps the orientations
+ * d = 1..D; every second step of one call runs backwards (reversed subdomain
+ * and orientation order), so an even nsteps is symmetric.  Colour classes:
+ * per direction the subdomain indices modulo k (k = 2 along the face-centred
+ * normal and without overlap, 3 with overlap), on a periodic direction whose
+ * count is not a multiple of k the last (count mod k) indices one by one;
+ * classes in lexicographic order of their per-direction colours (direction 1
+ * fastest).  u is updated in place; f unchanged. */
 int dgmg_smooth(dgmg_handle* h, int level, void* u, const void* f, int nsteps, int dtype);
 
 /* One additive Schwarz sweep over one partition of level l >= 1 (Sec. 3.1):
  * u += sum_s R_s^T (w_s (.) A_ss^{-1} R_s (f - A_l u)).  normal = -1: the
  * element-centred partition; normal = d: the face-centred partition with
  * faces normal to direction d.  Either kind may be used whatever the
- * handle's smoother (DGMG_EUNSUPPORTED if no patch kernel exists for the
- * tile).  Uses the level's internal residual scratch. */
+ * handle's additive smoother (DGMG_EUNSUPPORTED if no patch kernel exists
+ * for the tile).  A multiplicative handle (EM, FM) runs one forward
+ * multiplicative sweep instead, over its own kind of partition only
+ * (DGMG_EINVAL otherwise).  Uses the level's internal residual scratch. */
 int dgmg_sweep(dgmg_handle* h, int level, void* u, const void* f, int normal, int dtype);
 
 /* f_{l-1} = I_l^T r_l: restriction by the transpose of the embedded

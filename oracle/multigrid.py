@@ -100,7 +100,8 @@ class Hierarchy:
                     applyA = (lambda P_, ops_: (lambda u: apply_kron(grid, P_, u, ops=ops_)))(Pl, ops)
                 sm = SmootherLevel(grid, Pl, overlap_for(Pl, method.overlap), method.weighting,
                                    method.smoother, applyA, A, ops, mode=patch_mode,
-                                   face_params=None if face_params is None else face_params.get(l))
+                                   face_params=None if face_params is None else face_params.get(l),
+                                   order=getattr(method, "order", "lex"))
             self.levels.append(Level(Pl, A, sm, ops))
         A0 = self.levels[0].A
         self.periodic_any = all(grid.periodic)
@@ -148,10 +149,12 @@ class Hierarchy:
             return x - x.mean()
         return self._lu0.solve(f0)
 
-    def smooth(self, l: int, u, f, steps: int):
+    def smooth(self, l: int, u, f, steps: int, start: int = 0):
+        """`steps` smoothing iterations on level l (the multiplicative smoothers
+        alternate their direction within the call, starting forwards)."""
         if steps <= 0:
             return u
-        return self.levels[l].smoother.smooth(u, f, steps)
+        return self.levels[l].smoother.smooth(u, f, steps, start)
 
     def vcycle(self, u: np.ndarray, f: np.ndarray) -> np.ndarray:
         """MultigridCycle(u, f, N_S) of Alg. 1."""

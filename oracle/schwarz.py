@@ -26,6 +26,23 @@ phi(|xi_F|) does not.
 
 Sweeps: EA = one additive sweep over all EC patches; FA = one additive sweep
 per orientation d = 1..D in sequence, the residual recomputed before each.
+
+Multiplicative Schwarz (EM, FM; Sec. 3.1): the subproblems of a partition are
+solved one after another, each on the residual left by the previous ones, and
+the correction added unweighted: u <- u + R_s^T A_ss^-1 R_s (g - A u).  EM: one
+sweep over the element-centred subdomains per iteration; FM: one sweep per
+orientation d = 1..D.  Within a partition the subdomains are taken in
+lexicographic order (direction 1 fastest, as the elements are numbered).  Within
+one smoothing call every second iteration runs backwards: reversed subdomain
+order and, face-centred, reversed orientation order, so that a call with an
+even number of iterations is symmetric (Sec. 3.1); with one iteration per call,
+as in V(1,1), pre- and post-smoothing both sweep forwards (the reading under
+which Table 2's MG rows with EM_0 and FM_0 are reproduced; running the
+post-smoothing backwards gives r = 0.42 instead of the printed 0.63 for EM_0 at
+P = 4).  order = "colour" takes the same steps in another order:
+subdomains grouped in colour classes whose members share no node and no matrix
+entry (so the members of one class could be solved at once), the classes in
+lexicographic order of their colours, a class's members lexicographically.
 """
 from __future__ import annotations
 
@@ -158,6 +175,30 @@ def fc_patches_1d(P: int, N: int, periodic: bool, kind: str, theta=None, omega=N
     return out
 
 
+# --------------------------------------------------------------------------- multiplicative order
+
+def colour_modulus(n_o: int, normal: bool) -> int:
+    """Colours per direction of the multiplicative colour classes: two subdomains
+    of one colour must lie k apart.  Face-centred normal direction: faces f and
+    f + 2 share neither a node nor a matrix entry (the near half of an element
+    couples to its neighbour only through that neighbour's first node), k = 2;
+    element-centred / lateral extent without overlap: elements two apart are not
+    coupled, k = 2; with overlap a subdomain reaches N_O <= P nodes into both
+    neighbours, so three apart, k = 3."""
+    if normal or n_o == 0:
+        return 2
+    return 3
+
+
+def colour_digit(c: int, N: int, k: int, periodic: bool) -> int:
+    """Colour of subdomain index c (0 <= c < N) along one direction: c mod k; on a
+    periodic direction whose count N is not a multiple of k, the last N mod k
+    indices get colours of their own (k, k + 1, ...), so that two subdomains of
+    one colour stay k apart across the wrap as well."""
+    r = N % k if periodic else 0
+    return c % k if c < N - r else k + (c - (N - r))
+
+
 # --------------------------------------------------------------------------- level context
 
 def overlap_for(P_l: int, overlap) -> int:
@@ -185,7 +226,7 @@ class SmootherLevel:
     P: int
     n_o: int
     kind: str
-    smoother: str            # "EA" or "FA"
+    smoother: str            # "EA", "FA" (weighted additive) or "EM", "FM" (multiplicative)
     apply_A: object          # callable u_lex -> A u_lex
     A: object                # sparse matrix (lex) or None
     ops: list                # per direction (Mvec, Ldense)
@@ -193,6 +234,7 @@ class SmootherLevel:
     ec: list = field(default_factory=list)     # per direction list[Patch1D]
     fc: list = field(default_factory=list)
     face_params: Optional[list] = None        # per direction (theta[nf], omega[nf]) or None
+    order: str = "lex"                        # multiplicative subdomain order: "lex" or "colour"
     _eig: Dict = field(default_factory=dict)
     _chol: Dict = field(default_factory=dict)
 
@@ -333,8 +375,68 @@ class SmootherLevel:
             out.append(val)
         return np.asarray(out)
 
-    def smooth(self, u: np.ndarray, f: np.ndarray, steps: int) -> np.ndarray:
-        """`steps` Schwarz iterations (EA: one sweep each; FA: one sweep per direction)."""
+    # ---- multiplicative Schwarz
+    def mult_order(self, normal: int):
+        """Subdomains of one partition in the order of a forward multiplicative sweep."""
+        dim = self.grid.dim
+        counts = [len(self.fc[d]) if d == normal else len(self.ec[d]) for d in range(dim)]
+        lex = []
+        for combo in np.ndindex(*reversed(counts)):          # direction dim-1 slowest, 0 fastest
+            lex.append(tuple(reversed(combo)))
+        if self.order == "colour":
+            def key(c):
+                col = tuple(colour_digit(c[d], counts[d], colour_modulus(self.n_o, d == normal),
+                                         self.grid.periodic[d]) for d in reversed(range(dim)))
+                return col
+            lex = sorted(lex, key=key)                        # stable: lexicographic within a class
+        elif self.order != "lex":
+            raise ValueError(self.order)
+        return [tuple(("fc", c[d]) if d == normal else ("ec", c[d]) for d in range(dim)) for c in lex]
+
+    def msweep(self, u: np.ndarray, f: np.ndarray, normal: int, reverse: bool) -> np.ndarray:
+        """One multiplicative sweep over a partition (reverse: backwards)."""
+        dim = self.grid.dim
+        shape = self.shape
+        strides = [1]
+        for d in range(dim - 1):
+            strides.append(strides[-1] * shape[dim - 1 - d])
+        u = np.array(u, dtype=np.float64, copy=True)
+        order = self.mult_order(normal)
+        if reverse:
+            order = order[::-1]
+        for sig in order:
+            p1 = [self.patch_1d(d, sig[d]) for d in range(dim)]
+            gidx = np.zeros([len(p1[d].idx) for d in reversed(range(dim))], dtype=np.int64)
+            for d in range(dim):
+                ax = dim - 1 - d
+                sh = [1] * dim
+                sh[ax] = -1
+                gidx = gidx + (p1[d].idx * strides[d]).reshape(sh)
+            pshape = gidx.shape
+            gidx = gidx.reshape(-1)
+            if self.A is not None:
+                rs = f[gidx] - self.A[gidx] @ u
+            else:
+                rs = (f - self.apply_A(u))[gidx]
+            du = self.solve_patch(sig, rs.reshape(pshape), gidx)
+            u[gidx] += du.reshape(-1)               # indices are distinct within one patch
+        return u
+
+    def smooth(self, u: np.ndarray, f: np.ndarray, steps: int, start: int = 0) -> np.ndarray:
+        """`steps` Schwarz iterations (EA, EM: one sweep each; FA, FM: one sweep per
+        direction).  Multiplicative: iteration t = start, start + 1, ... runs
+        forwards for even t, backwards for odd t."""
+        if self.smoother in ("EM", "FM"):
+            dim = self.grid.dim
+            for i in range(steps):
+                rev = (start + i) % 2 == 1
+                if self.smoother == "EM":
+                    u = self.msweep(u, f, -1, rev)
+                else:
+                    dirs = list(range(dim))
+                    for d in (dirs[::-1] if rev else dirs):
+                        u = self.msweep(u, f, d, rev)
+            return u
         for _ in range(steps):
             if self.smoother == "EA":
                 u = self.sweep(u, f, normal=-1)

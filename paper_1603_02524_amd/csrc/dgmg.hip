@@ -337,6 +337,14 @@ struct dgmg_handle {
   hipStream_t cap_stream = nullptr;  // private stream used only while capturing
   // per-face (theta, omega) of the face-centred normal weights; empty = the fixed weights
   std::vector<double> face_theta, face_omega;
+  // multiplicative smoothers: per level and sweep kind the patch launches of
+  // one forward sweep, in order (colour classes, or single patches in
+  // lexicographic order)
+  struct MultClass {
+    PatchLat lat;
+    int n[3] = {1, 1, 1};
+  };
+  std::vector<MultClass> mcls[MAXL][NKIND];
   // autotuned patch-solve block shapes (waves per block), 0 = default
   int waves[MAXL][NKIND] = {};
   float tune_ms[MAXL][NKIND] = {};
@@ -386,6 +394,61 @@ int check_hip(dgmg_handle* h, const char* where) {
 }
 
 bool mixed(const dgmg_handle* h) { return h->opts.precision == DGMG_PREC_MIXED; }
+bool ec_smoother(const dgmg_handle* h) {
+  return h->opts.smoother == DGMG_SMOOTHER_EA || h->opts.smoother == DGMG_SMOOTHER_EM;
+}
+bool multiplicative(const dgmg_handle* h) {
+  return h->opts.smoother == DGMG_SMOOTHER_EM || h->opts.smoother == DGMG_SMOOTHER_FM;
+}
+
+// Patch launches of one forward multiplicative sweep (Sec. 3.1) on a level,
+// normal nd (-1: element-centred).  Per direction the patch indices are split
+// into groups: ORDER_LEX one group per patch (the lexicographic order,
+// direction 0 fastest); ORDER_COLOUR the residues mod k (k = 2 along the
+// face-centred normal and without overlap, 3 with overlap: patches k apart
+// share no node and no matrix entry) followed, on a periodic direction whose
+// count is not a multiple of k, by the last count mod k patches one by one.
+// A launch is one group per direction; launches run with direction 0's group
+// fastest.
+std::vector<dgmg_handle::MultClass> mult_classes(const LevelHost& lv, int nd, int order) {
+  struct Grp {
+    int start, stride, count;
+  };
+  std::vector<Grp> grp[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d >= lv.dim) {
+      grp[d].push_back({0, 1, 1});
+      continue;
+    }
+    const Dir1D& s = lv.dir[d];
+    const int cnt = d == nd ? s.nf : s.N;
+    if (order == DGMG_ORDER_LEX) {
+      for (int c = 0; c < cnt; ++c) grp[d].push_back({c, 1, 1});
+      continue;
+    }
+    const int k = (d == nd || lv.NO == 0) ? 2 : 3;
+    const int rem = s.periodic ? cnt % k : 0;
+    for (int j = 0; j < k; ++j) {
+      const int m = (cnt - rem - j + k - 1) / k;
+      if (m > 0) grp[d].push_back({j, k, m});
+    }
+    for (int i = 0; i < rem; ++i) grp[d].push_back({cnt - rem + i, 1, 1});
+  }
+  std::vector<dgmg_handle::MultClass> out;
+  for (const Grp& g2 : grp[2])
+    for (const Grp& g1 : grp[1])
+      for (const Grp& g0 : grp[0]) {
+        dgmg_handle::MultClass c;
+        const Grp* g[3] = {&g0, &g1, &g2};
+        for (int d = 0; d < 3; ++d) {
+          c.lat.start[d] = g[d]->start;
+          c.lat.stride[d] = g[d]->stride;
+          c.n[d] = g[d]->count;
+        }
+        out.push_back(c);
+      }
+  return out;
+}
 size_t mg_size(const dgmg_handle* h) { return mixed(h) ? sizeof(float) : sizeof(double); }
 
 // Workspace carving: a dry run (base == nullptr) computes the size.
@@ -606,8 +669,9 @@ int k_fdm(dgmg_handle* h, int l, int nd, const T* r, int waves) {
   int np[3], NA, NL;
   sweep_shape(h->lv[l], nd, np, NA, NL);
   T* pb = (T*)h->patch;
-  int rc = L.dim == 3 ? Kern<T, 3>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, h->stream)
-                      : Kern<T, 2>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, h->stream);
+  const PatchLat all;
+  int rc = L.dim == 3 ? Kern<T, 3>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, all, h->stream)
+                      : Kern<T, 2>::fdm(L, nd, NA, NL, r, pb, np[0], np[1], np[2], waves, all, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no patch-solve kernel for this tile");
   return DGMG_OK;
 }
@@ -669,11 +733,68 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero =
   return check_hip(h, "combine");
 }
 
+template <class T>
+void k_fill_v(dgmg_handle* h, T* a, int64_t n, T v = T(0)) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, v, n, h->active);
+}
+
+// One multiplicative sweep (Sec. 3.1): the patch launches of the level's
+// order (reversed when `reverse`), each on the residual left by the previous
+// ones: r = f - A u, the launch's patch solves, u += their corrections
+// (unweighted; the weight tables of a multiplicative handle are 1).
+// u_zero: u is taken as 0 on entry (it is cleared; the first launch reads f).
+template <class T>
+int k_msweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool reverse, bool u_zero) {
+  const LevelDev<T>& L = LD<T>(h, l);
+  const LevelHost& lv = h->lv[l];
+  int np[3], NA, NL;
+  sweep_shape(lv, nd, np, NA, NL);
+  const int kind = nd < 0 ? 3 : nd;
+  const auto& cls = h->mcls[l][kind];
+  if (u_zero) k_fill_v<T>(h, u, lv.n_dof);
+  T* pb = (T*)h->patch;
+  const int nc = (int)cls.size();
+  for (int i = 0; i < nc; ++i) {
+    const dgmg_handle::MultClass& c = cls[reverse ? nc - 1 - i : i];
+    const bool first = u_zero && i == 0;
+    int rc = first ? DGMG_OK : k_apply<T>(h, l, 1, u, f, r, nullptr, nullptr);
+    if (rc) return rc;
+    const T* res = first ? f : r;
+    rc = L.dim == 3
+             ? Kern<T, 3>::fdm(L, nd, NA, NL, res, pb, c.n[0], c.n[1], c.n[2], h->waves[l][kind], c.lat, h->stream)
+             : Kern<T, 2>::fdm(L, nd, NA, NL, res, pb, c.n[0], c.n[1], c.n[2], h->waves[l][kind], c.lat, h->stream);
+    if (rc) return fail(h, DGMG_EUNSUPPORTED, "no patch-solve kernel for this multiplicative sweep");
+    rc = L.dim == 3 ? Kern<T, 3>::mult_update(L, nd, NA, NL, c.lat, c.n[0], c.n[1], c.n[2], pb, u, h->stream)
+                    : Kern<T, 2>::mult_update(L, nd, NA, NL, c.lat, c.n[0], c.n[1], c.n[2], pb, u, h->stream);
+    if (rc) return fail(h, DGMG_EUNSUPPORTED, "multiplicative update");
+  }
+  return check_hip(h, "multiplicative sweep");
+}
+
 // `steps` smoothing steps (EA: one sweep; FA: one sweep per direction).
+// Multiplicative (EM, FM): within the call every second step runs backwards
+// (reversed patch order and, FM, reversed sweep directions), so that an even
+// number of steps is symmetric (Sec. 3.1).
 // u_zero: u is taken as 0 on entry, whatever it holds (the first sweep skips
 // its residual apply and assigns u); needs steps >= 1.
 template <class T>
 int k_smooth(dgmg_handle* h, int l, T* u, const T* f, int steps, T* r, bool u_zero = false) {
+  if (multiplicative(h)) {
+    const int dim = h->lv[l].dim;
+    for (int s = 0; s < steps; ++s) {
+      const bool rev = s % 2 == 1;
+      if (ec_smoother(h)) {
+        int rc = k_msweep<T>(h, l, -1, u, f, r, rev, u_zero && s == 0);
+        if (rc) return rc;
+        continue;
+      }
+      for (int i = 0; i < dim; ++i) {
+        int rc = k_msweep<T>(h, l, rev ? dim - 1 - i : i, u, f, r, rev, u_zero && s == 0 && i == 0);
+        if (rc) return rc;
+      }
+    }
+    return DGMG_OK;
+  }
   for (int s = 0; s < steps; ++s) {
     if (h->opts.smoother == DGMG_SMOOTHER_EA) {
       int rc = k_sweep<T>(h, l, -1, u, f, r, u_zero && s == 0);
@@ -715,10 +836,6 @@ int k_residual_restrict(dgmg_handle* h, int l, const T* u, const T* f, T* r_scra
   return k_transfer<T>(h, l, true, r_scratch, fc);
 }
 
-template <class T>
-void k_fill_v(dgmg_handle* h, T* a, int64_t n, T v = T(0)) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(vec_blocks(n)), dim3(VEC_THREADS), 0, h->stream, a, v, n, h->active);
-}
 
 // sum of a (n doubles) into *out, using c_a as a vector of ones
 void k_mean_sub(dgmg_handle* h, double* a, int64_t n) {
@@ -1030,7 +1147,9 @@ int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
     return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16, 32");
   if (!(o->mu_star > 0) || !std::isfinite(o->mu_star)) return fail(nullptr, DGMG_EINVAL, "mu_star must be > 0");
   if (o->flux != DGMG_FLUX_IP && o->flux != DGMG_FLUX_LDG) return fail(nullptr, DGMG_EINVAL, "bad flux");
-  if (o->smoother != DGMG_SMOOTHER_EA && o->smoother != DGMG_SMOOTHER_FA) return fail(nullptr, DGMG_EINVAL, "bad smoother");
+  if (o->smoother < DGMG_SMOOTHER_EA || o->smoother > DGMG_SMOOTHER_FM) return fail(nullptr, DGMG_EINVAL, "bad smoother");
+  if (o->order != DGMG_ORDER_LEX && o->order != DGMG_ORDER_COLOUR) return fail(nullptr, DGMG_EINVAL, "bad order");
+  const bool mult = o->smoother == DGMG_SMOOTHER_EM || o->smoother == DGMG_SMOOTHER_FM;
   if (o->weighting < 0 || o->weighting > 3) return fail(nullptr, DGMG_EINVAL, "bad weighting");
   if (o->vcycle != DGMG_VCYCLE_CLASSICAL && o->vcycle != DGMG_VCYCLE_VARIABLE) return fail(nullptr, DGMG_EINVAL, "bad vcycle");
   if (o->precision != DGMG_PREC_FP64 && o->precision != DGMG_PREC_MIXED) return fail(nullptr, DGMG_EINVAL, "bad precision");
@@ -1058,7 +1177,8 @@ int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   sp.mu_star = o->mu_star;
   sp.smoother = o->smoother;
   sp.overlap = o->overlap;
-  sp.weighting = o->weighting;
+  // multiplicative Schwarz adds its corrections unweighted: unit weight tables
+  sp.weighting = mult ? DGMG_WEIGHT_NONE : o->weighting;
   return DGMG_OK;
 }
 
@@ -1073,9 +1193,9 @@ int autotune_t(dgmg_handle* h) {
   for (int l = 1; l < nl && !rc; ++l) {
     T* r = (T*)h->buf[l].r;
     k_fill_v<T>(h, r, h->lv[l].n_dof);
-    const int nkinds = h->opts.smoother == DGMG_SMOOTHER_EA ? 1 : h->lv[l].dim;
+    const int nkinds = ec_smoother(h) ? 1 : h->lv[l].dim;
     for (int q = 0; q < nkinds && !rc; ++q) {
-      const int nd = h->opts.smoother == DGMG_SMOOTHER_EA ? -1 : q;
+      const int nd = ec_smoother(h) ? -1 : q;
       const int kind = nd < 0 ? 3 : nd;
       float best = 1e30f;
       int bw = 0;
@@ -1159,14 +1279,27 @@ int dgmg_setup(const dgmg_grid* g, const dgmg_opts* o, dgmg_handle** out) {
   for (size_t l = 1; l < h->lv.size(); ++l) {  // kernels must exist for every smoothing level
     const LevelHost& lv = h->lv[l];
     const int NL = lv.NP + 2 * lv.NO;
-    const int NA = o->smoother == DGMG_SMOOTHER_EA ? NL : 2 * lv.P;
+    const int NA = (o->smoother == DGMG_SMOOTHER_EA || o->smoother == DGMG_SMOOTHER_EM) ? NL : 2 * lv.P;
     const bool ok = g->dim == 3 ? Kern<double, 3>::fdm_supported(NA, NL) : Kern<double, 2>::fdm_supported(NA, NL);
     if (!ok) {
       delete h;
       return fail(nullptr, DGMG_EUNSUPPORTED,
                   "no patch kernel for P_l=" + std::to_string(lv.P) + " N_O=" + std::to_string(lv.NO));
     }
+    // the multiplicative launches take subsets of the patches: only the tiles that fit in LDS
+    if (multiplicative(h) && g->dim == 3 && !Kern<double, 3>::fdm_in_lds(NA, NL)) {
+      delete h;
+      return fail(nullptr, DGMG_EUNSUPPORTED,
+                  "multiplicative smoothers: the patch tile of P_l=" + std::to_string(lv.P) +
+                      " exceeds LDS (its large-tile solve takes whole partitions only)");
+    }
   }
+  if (multiplicative(h))
+    for (size_t l = 1; l < h->lv.size(); ++l) {
+      if (ec_smoother(h)) h->mcls[l][3] = mult_classes(h->lv[l], -1, o->order);
+      else
+        for (int d = 0; d < h->lv[l].dim; ++d) h->mcls[l][d] = mult_classes(h->lv[l], d, o->order);
+    }
   layout(h, nullptr, nullptr);
   *out = h;
   return DGMG_OK;
@@ -1275,6 +1408,13 @@ int dgmg_sweep(dgmg_handle* h, int level, void* u, const void* f, int normal, in
   sweep_shape(lv, normal, np, NA, NL);
   const bool ok = lv.dim == 3 ? Kern<double, 3>::fdm_supported(NA, NL) : Kern<double, 2>::fdm_supported(NA, NL);
   if (!ok) return fail(h, DGMG_EUNSUPPORTED, "no patch kernel for this sweep");
+  if (multiplicative(h) && (normal < 0) != ec_smoother(h))
+    return fail(h, DGMG_EINVAL, "normal does not match the multiplicative smoother's subdomains");
+  if (multiplicative(h)) {
+    if (dtype == DGMG_F64)
+      return k_msweep<double>(h, level, normal, (double*)u, (const double*)f, (double*)h->buf[level].r, false, false);
+    return k_msweep<float>(h, level, normal, (float*)u, (const float*)f, (float*)h->buf[level].r, false, false);
+  }
   if (dtype == DGMG_F64)
     return k_sweep<double>(h, level, normal, (double*)u, (const double*)f, (double*)h->buf[level].r);
   return k_sweep<float>(h, level, normal, (float*)u, (const float*)f, (float*)h->buf[level].r);
@@ -1779,9 +1919,9 @@ int dgmg_batch_autotune(dgmg_batch* b) {
   std::vector<std::pair<std::vector<int64_t>, int>> seen;
   for (dgmg_handle* h : b->h) {
     for (int l = 1; l < (int)h->lv.size(); ++l) {
-      const int nk = h->opts.smoother == DGMG_SMOOTHER_EA ? 1 : h->lv[l].dim;
+      const int nk = ec_smoother(h) ? 1 : h->lv[l].dim;
       for (int q = 0; q < nk; ++q) {
-        const int nd = h->opts.smoother == DGMG_SMOOTHER_EA ? -1 : q;
+        const int nd = ec_smoother(h) ? -1 : q;
         int np[3], NA, NL;
         sweep_shape(h->lv[l], nd, np, NA, NL);
         std::vector<int64_t> key{(int64_t)mg_size(h), h->lv[l].dim, NA, NL, np[0], np[1], np[2]};

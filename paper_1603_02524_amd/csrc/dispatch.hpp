@@ -48,18 +48,35 @@ bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
 }
 
 template <class T, int DIM>
+bool Kern<T, DIM>::fdm_in_lds(int NA, int NL) {
+#define DGMG_CASE(A, B) \
+  if (NA == A && NL == B) return !(DIM == 3 && fdm_lds_total<T, A, B, DIM>() > LDS_BYTES);
+  DGMG_FDM_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return false;
+}
+
+template <class T, int DIM>
 int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx,
-                      int npy, int npz, int waves, hipStream_t s) {
+                      int npy, int npz, int waves, const PatchLat& lat, hipStream_t s) {
+  const bool whole = lat.start[0] == 0 && lat.start[1] == 0 && lat.start[2] == 0 && lat.stride[0] == 1 &&
+                     lat.stride[1] == 1 && lat.stride[2] == 1;
 #define DGMG_CASE(A, B)                                                                   \
   if (NA == A && NL == B) {                                                               \
     if constexpr (DIM == 3 && fdm_lds_total<T, A, B, DIM>() > LDS_BYTES)                  \
-      return fdm_big_launch<T, A, B>(L, nd, r, out, npx, npy, npz, s);                    \
+      return whole ? fdm_big_launch<T, A, B>(L, nd, r, out, npx, npy, npz, s) : -4;       \
     else                                                                                  \
-      return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, s);          \
+      return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, lat, s);     \
   }
   DGMG_FDM_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::mult_update(const LevelDev<T>& L, int nd, int NA, int NL, const PatchLat& lat, int npx,
+                              int npy, int npz, const T* buf, T* u, hipStream_t s) {
+  return mult_update_launch<T, DIM>(L, nd, NA, NL, lat, npx, npy, npz, buf, u, s);
 }
 
 template <class T, int DIM>

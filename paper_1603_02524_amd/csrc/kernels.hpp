@@ -75,6 +75,14 @@ struct LevelDev {
 
 __device__ __forceinline__ bool inactive(const int* flag) { return flag != nullptr && *flag == 0; }
 
+// Patches of one launch: per direction the patch indices start + stride * k,
+// k = 0 .. count - 1 (the additive sweeps take all of them: start 0, stride 1;
+// a colour class of the multiplicative smoothers takes every k-th).
+struct PatchLat {
+  int start[3] = {0, 0, 0};
+  int stride[3] = {1, 1, 1};
+};
+
 // ---------------------------------------------------------------- block reduction
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -838,7 +846,7 @@ constexpr int fdm_min_waves() {
 }
 template <class T, int DIM, int NA, int NL, int ND>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_min_waves<NA, NL>()))) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
-                                                  int npx, int npy, int npz) {
+                                                  int npx, int npy, int npz, PatchLat lat) {
   using S = FdmShape<DIM, ND, NA, NL>;
   constexpr int TS = S::TS;
   constexpr int NMAX = imax(NA, NL);
@@ -857,9 +865,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
   if (pid < 0 || inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   int p[3];
-  p[0] = pid % npx;
-  p[1] = (pid / npx) % npy;
-  p[2] = DIM == 3 ? pid / (npx * npy) : 0;
+  p[0] = lat.start[0] + lat.stride[0] * (pid % npx);
+  p[1] = lat.start[1] + lat.stride[1] * ((pid / npx) % npy);
+  p[2] = DIM == 3 ? lat.start[2] + lat.stride[2] * (pid / (npx * npy)) : 0;
   const int* go[3] = {nullptr, nullptr, nullptr};
   const T* wg[3] = {nullptr, nullptr, nullptr};
 #pragma unroll
@@ -1059,32 +1067,77 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
 
 template <class T, int DIM, int NA, int NL, int ND>
 void fdm_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, int npz, int th, size_t shm,
-                   hipStream_t s) {
+                   const PatchLat& lat, hipStream_t s) {
   const int npatch = npx * npy * (DIM == 3 ? npz : 1);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL, ND>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
   hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL, ND>), dim3(xcd_grid(npatch)), dim3(th), shm, s, L, r, out, npx, npy,
-                     npz);
+                     npz, lat);
 }
 
 // waves: wavefronts per block (1 .. 8; 0 = default), the shape the autotuner picks.
 template <class T, int DIM, int NA, int NL>
 int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
-                 int waves, hipStream_t s) {
+                 int waves, const PatchLat& lat, hipStream_t s) {
   constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
   const int th = (waves >= 1 && waves <= 8) ? 64 * waves : fdm_threads<NA, NL, DIM>();
   if (nd < 0) {
     if constexpr (NA == NL) {
-      fdm_launch_nd<T, DIM, NA, NL, -1>(L, r, out, npx, npy, npz, th, shm, s);
+      fdm_launch_nd<T, DIM, NA, NL, -1>(L, r, out, npx, npy, npz, th, shm, lat, s);
       return 0;
     }
     return -4;
   }
-  if (nd == 0) fdm_launch_nd<T, DIM, NA, NL, 0>(L, r, out, npx, npy, npz, th, shm, s);
-  else if (nd == 1) fdm_launch_nd<T, DIM, NA, NL, 1>(L, r, out, npx, npy, npz, th, shm, s);
-  else if constexpr (DIM == 3) fdm_launch_nd<T, DIM, NA, NL, 2>(L, r, out, npx, npy, npz, th, shm, s);
+  if (nd == 0) fdm_launch_nd<T, DIM, NA, NL, 0>(L, r, out, npx, npy, npz, th, shm, lat, s);
+  else if (nd == 1) fdm_launch_nd<T, DIM, NA, NL, 1>(L, r, out, npx, npy, npz, th, shm, lat, s);
+  else if constexpr (DIM == 3) fdm_launch_nd<T, DIM, NA, NL, 2>(L, r, out, npx, npy, npz, th, shm, lat, s);
   else return -4;
+  return 0;
+}
+
+// ================================================================ multiplicative update
+// u += R_s^T Delta u_s, unweighted, for the patches of one launch of the patch
+// solve (a colour class: their node sets are disjoint, so every node receives
+// at most one value and no two threads write the same entry).  One block per
+// patch (its index among the launch's patches, as the patch solve numbered
+// them), threads over its tile in grid-natural order; positions outside a
+// Dirichlet domain are skipped.
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) mult_update_kernel(LevelDev<T> L, int nd, int NA, int NL, PatchLat lat,
+                                                          int npx, int npy, const T* __restrict__ buf,
+                                                          T* __restrict__ u) {
+  if (inactive(L.active)) return;
+  const int pid = blockIdx.x;
+  int p[3];
+  p[0] = lat.start[0] + lat.stride[0] * (pid % npx);
+  p[1] = lat.start[1] + lat.stride[1] * ((pid / npx) % npy);
+  p[2] = DIM == 3 ? lat.start[2] + lat.stride[2] * (pid / (npx * npy)) : 0;
+  const int* go[3] = {nullptr, nullptr, nullptr};
+  int len[3] = {1, 1, 1};
+  for (int d = 0; d < DIM; ++d) {
+    const bool fc = d == nd;
+    len[d] = fc ? NA : NL;
+    go[d] = fc ? L.dir[d].goff_fc + p[d] * NA : L.dir[d].goff_ec + p[d] * NL;
+  }
+  const int ts = len[0] * len[1] * len[2];
+  const T* src = buf + (int64_t)pid * ts;
+  for (int q = threadIdx.x; q < ts; q += blockDim.x) {
+    const int o0 = q % len[0], rw = q / len[0];
+    const int o1 = rw % len[1], o2 = rw / len[1];
+    const int g0 = go[0][o0], g1 = go[1][o1], g2 = DIM == 3 ? go[2][o2] : 0;
+    if ((g0 | g1 | g2) < 0) continue;
+    u[g0 + g1 + g2] += src[q];
+  }
+}
+
+template <class T, int DIM>
+int mult_update_launch(const LevelDev<T>& L, int nd, int NA, int NL, const PatchLat& lat, int npx, int npy,
+                       int npz, const T* buf, T* u, hipStream_t s) {
+  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+  if (npatch <= 0) return 0;
+  hipLaunchKernelGGL((mult_update_kernel<T, DIM>), dim3(npatch), dim3(256), 0, s, L, nd, NA, NL, lat, npx, npy, buf,
+                     u);
   return 0;
 }
 
@@ -1311,9 +1364,16 @@ struct Kern {
   // it is not built (large elements): the caller then runs mode 1 and transfer.
   static int apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
                    int* nblk, hipStream_t s);
+  // lat: the patches of this launch (all of them: PatchLat{}); large tiles
+  // (3D P = 32) take only the whole partition
   static int fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, T* out, int npx, int npy,
-                 int npz, int waves, hipStream_t s);
+                 int npz, int waves, const PatchLat& lat, hipStream_t s);
+  // u += the unweighted corrections of one patch-solve launch (disjoint patches)
+  static int mult_update(const LevelDev<T>& L, int nd, int NA, int NL, const PatchLat& lat, int npx, int npy,
+                         int npz, const T* buf, T* u, hipStream_t s);
   static bool fdm_supported(int NA, int NL);
+  // the tile's solve runs in LDS (not the large-tile stages through global memory)
+  static bool fdm_in_lds(int NA, int NL);
   // assign: u = the overlap sum (u is zero on entry) instead of u += it
   static int combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, bool assign, hipStream_t s);

@@ -20,7 +20,8 @@ OK, NOT_CONVERGED, FELLBACK = 0, 1, 2
 F64, F32 = 0, 1
 
 _FLUX = {"ip": 0, "ldg": 1}
-_SMOOTHER = {"EA": 0, "FA": 1}
+_SMOOTHER = {"EA": 0, "FA": 1, "EM": 2, "FM": 3}
+_ORDER = {"lex": 0, "colour": 1}
 _WEIGHT = {"quintic": 0, "cubic": 1, "arith": 2, "none": 3}
 _VCYCLE = {"classical": 0, "variable": 1}
 _PREC = {"fp64": 0, "mixed": 1}
@@ -34,7 +35,8 @@ class DgmgGrid(ctypes.Structure):
 class DgmgOpts(ctypes.Structure):
     _fields_ = [("P", c_int), ("flux", c_int), ("beta", c_double * 3), ("mu_star", c_double),
                 ("smoother", c_int), ("overlap", c_int), ("weighting", c_int), ("vcycle", c_int),
-                ("ns_pre", c_int), ("ns_post", c_int), ("precision", c_int), ("max_iter", c_int)]
+                ("ns_pre", c_int), ("ns_post", c_int), ("precision", c_int), ("max_iter", c_int),
+                ("order", c_int)]
 
 
 class DgmgStats(ctypes.Structure):
@@ -151,6 +153,7 @@ def make_structs(grid, method, max_iter: int = 100):
     o.ns_pre, o.ns_post = int(method.ns[0]), int(method.ns[1])
     o.precision = _PREC[method.precision]
     o.max_iter = int(max_iter)
+    o.order = _ORDER[getattr(method, "order", "lex")]
     return g, o, keep
 
 
@@ -259,7 +262,8 @@ class Solver:
         return u
 
     def sweep(self, level, u, f, normal=-1):
-        """One additive Schwarz sweep in place on u (normal -1: element-centred)."""
+        """One Schwarz sweep in place on u (normal -1: element-centred); multiplicative
+        handles sweep their own partition forwards."""
         self._check(self.lib.dgmg_sweep(self.h, level, self._ptr(u), self._ptr(f), int(normal),
                                         self._dtype_code(u)))
         return u

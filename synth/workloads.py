@@ -50,10 +50,13 @@ class Method:
     """Solver options (names follow the paper's notation).
 
     flux: "ip" or "ldg"; beta: per-direction LDG parameter; mu_star: penalty
-    factor; smoother: "EA" (element-centred additive) or "FA" (face-centred
-    additive); overlap: "level" (N_O = 1 + floor(P_l/8)), "zero", or an int;
-    weighting: "quintic", "cubic", "arith", "none"; vcycle: "classical" or
-    "variable"; precision: "fp64" or "mixed".
+    factor; smoother: "EA" / "FA" (element- / face-centred weighted additive)
+    or "EM" / "FM" (element- / face-centred multiplicative); overlap: "level"
+    (N_O = 1 + P_l/8 rounded), "level_floor", "zero", or an int; weighting:
+    "quintic", "cubic", "arith", "none" (additive smoothers only); vcycle:
+    "classical" or "variable"; precision: "fp64" or "mixed"; order: subdomain
+    order of the multiplicative smoothers, "lex" (lexicographic, direction 1
+    fastest) or "colour" (colour classes of mutually independent subdomains).
     """
 
     P: int
@@ -67,6 +70,7 @@ class Method:
     ns: Tuple[int, int] = (1, 1)
     precision: str = "fp64"
     krylov: bool = True
+    order: str = "lex"
 
 
 @dataclass
@@ -183,11 +187,11 @@ def c5_poisson3d_p32(seed: int = 5, n: int = 8) -> Workload:
 
 def paper_periodic_2d(P: int, n: int = 16, ar: int = 1, smoother: str = "EA",
                       overlap: object = "level", beta: float = 0.0, weighting: str = "quintic",
-                      krylov: bool = True, vcycle: str = "classical") -> Workload:
+                      krylov: bool = True, vcycle: str = "classical", order: str = "lex") -> Workload:
     """The paper's test case: periodic (0, 2AR) x (0, 2), n x n equal elements."""
     g = uniform_grid(2, n, (2.0 * ar, 2.0), True)
     m = Method(P=P, flux="ip" if beta == 0.0 else "ldg", beta=(beta, beta), smoother=smoother,
-               overlap=overlap, weighting=weighting, krylov=krylov, vcycle=vcycle)
+               overlap=overlap, weighting=weighting, krylov=krylov, vcycle=vcycle, order=order)
     return Workload(f"periodic2d_{n}x{n}_ar{ar}_p{P}_{smoother}", g, m, 0, "manufactured")
 
 

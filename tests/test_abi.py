@@ -34,7 +34,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(D.DgmgStats) == 4 + 4 + 8 * 3 + 8 * 256 + 8 + 4 + 4  # r_true, replacements, tail padding
     # int dim; int n_elem[3]; const double* dx[3] (8-aligned at 16); int periodic[3]; tail pad
     assert ctypes.sizeof(D.DgmgGrid) == 56
-    assert ctypes.sizeof(D.DgmgOpts) == 4 + 4 + 24 + 8 + 4 * 8
+    assert ctypes.sizeof(D.DgmgOpts) == 4 + 4 + 24 + 8 + 4 * 9 + 4  # order; tail padding to 8
 
 
 def test_defaults():

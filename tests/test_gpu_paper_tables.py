@@ -5,8 +5,9 @@ The same golden rows as the oracle's test (tests/golden/paper_tables.json):
 f = 2 pi^2 sin(pi x) sin(pi y) at the GLL nodes (mean removed), random initial
 guess in [0, 1].  MGCG rows run dgmg_solve; multigrid-alone rows iterate
 u <- u + V(f - A u) with the library's residual and V-cycle.  Tolerances as for
-the oracle: mean convergence rate r_bar within 6 % (12 % for FA_l rows, which
-run about 5 % below print) and n10 within one cycle."""
+the oracle: mean convergence rate r_bar within 7 % and n10 within one cycle.
+Multiplicative rows (EM_0, FM_0) run the paper's lexicographic order: one
+patch per launch."""
 import json
 import os
 
@@ -34,7 +35,7 @@ def _rows():
 def _run(row, seed=1, i_max=400):
     w = synth.paper_periodic_2d(row["P"], n=row["n"], ar=row["ar"], smoother=row["smoother"],
                                 overlap=row["overlap"], beta=row["beta"], krylov=row["krylov"],
-                                weighting=row["weighting"], vcycle=row["vcycle"])
+                                weighting=row["weighting"], vcycle=row["vcycle"], order=row.get("order", "lex"))
     g, m = w.grid, w.method
     S = D.Solver(g, m, max_iter=i_max)
     try:
@@ -73,7 +74,7 @@ def test_gpu_reproduces_paper_rates(row):
     n10 = me.n10(hist)
     assert n10 is not None
     rb = me.r_bar(hist, n10)
-    tol = 0.12 if (row["smoother"] == "FA" and row["overlap"] == "level") else 0.06
+    tol = 0.07
     print(f"  r_bar {rb:.3f} (printed {row['r_bar']}), n10 {n10} (printed {row['n10']})")
     assert rb == pytest.approx(row["r_bar"], rel=tol), (rb, row["r_bar"])
     if row["n10"] is not None:
@@ -84,7 +85,7 @@ def _oracle_history(row, seed=1, i_max=400):
     """The oracle's run on the same data (CPU, FP64)."""
     w = synth.paper_periodic_2d(row["P"], n=row["n"], ar=row["ar"], smoother=row["smoother"],
                                 overlap=row["overlap"], beta=row["beta"], krylov=row["krylov"],
-                                weighting=row["weighting"], vcycle=row["vcycle"])
+                                weighting=row["weighting"], vcycle=row["vcycle"], order=row.get("order", "lex"))
     g, m = w.grid, w.method
     h = mg.Hierarchy(g, m, patch_mode="fdm")
     xs = [op.node_coords_1d(np.asarray(g.dx[d]), m.P) for d in range(2)]

@@ -69,7 +69,8 @@ def test_mgcg_reaches_tolerance_3d_dirichlet(smoother):
 def _paper_run(row, seed=1):
     w = synth.paper_periodic_2d(row["P"], n=row["n"], ar=row["ar"], smoother=row["smoother"],
                                 overlap=row["overlap"], beta=row["beta"], krylov=row["krylov"],
-                                weighting=row["weighting"], vcycle=row["vcycle"])
+                                weighting=row["weighting"], vcycle=row["vcycle"],
+                                order=row.get("order", "lex"))
     g, m = w.grid, w.method
     h = mg.Hierarchy(g, m, patch_mode="fdm")
     P = m.P
@@ -90,13 +91,12 @@ def _rows():
 
 @pytest.mark.parametrize("row", _rows(), ids=lambda r: r["cite"][:60])
 def test_paper_convergence_rates(row):
-    """r_bar within 12 % (FA_l rows run about 5 % below the printed values) and
-    n10 within one cycle of the printed tables."""
+    """r_bar within 7 % and n10 within one cycle of the printed tables."""
     res = _paper_run(row)
     n10 = me.n10(res.history)
     assert n10 is not None
     rb = me.r_bar(res.history, n10)
-    tol = 0.12 if (row["smoother"] == "FA" and row["overlap"] == "level") else 0.06
+    tol = 0.07
     assert rb == pytest.approx(row["r_bar"], rel=tol), (rb, row["r_bar"])
     if row["n10"] is not None:
         assert abs(n10 - row["n10"]) <= 1
