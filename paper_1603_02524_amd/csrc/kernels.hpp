@@ -18,15 +18,6 @@ constexpr int round64(int a) { return (a + 63) / 64 * 64; }
 
 constexpr int NUM_XCD = 8;  // MI355X: 8 accelerator complex dies, blocks dispatched round-robin
 
-// Patch-solve code shape: keep the 1D bases of tiles up to 16 long in registers
-// for the whole kernel, and the number of 16-line blocks a wave contracts at once.
-#ifndef DGMG_FDM_PRELOAD
-#define DGMG_FDM_PRELOAD 0
-#endif
-#ifndef DGMG_FDM_MBLK
-#define DGMG_FDM_MBLK 1
-#endif
-
 // Logical block index such that each XCD receives one contiguous range of
 // logical blocks (neighbouring elements then share that XCD's L2).  The grid
 // is launched with NUM_XCD * ceil(G / NUM_XCD) blocks; returns -1 for padding.
@@ -632,9 +623,8 @@ struct BOp {
 
 // One contraction pass over tile dimension TD: every line v (length LEN) is
 // replaced by B^T v, i.e. out_j = sum_k B[k][j] v_k.  The lines form the M
-// dimension in blocks of 16; each wave owns whole blocks and works on
-// DGMG_FDM_MBLK of them at a time (independent accumulation chains), reading
-// them (A operand) completely before writing them back in place.
+// dimension in blocks of 16; each wave owns whole blocks, reading a block
+// (A operand) completely before writing it back in place.
 struct NoPost {
   template <class T>
   __device__ __forceinline__ T operator()(int, int, T v) const { return v; }
@@ -663,71 +653,50 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ t
   constexpr int LINES = TD == 0 ? ipow(NL, DIM - 1) : NA * ipow(NL, DIM - 2);
   constexpr int STRIDE = TD == 0 ? 1 : (TD == 1 ? NAP : NAP * NL);
   constexpr int KS = BOp<T, LEN>::KS, NB = BOp<T, LEN>::NB, MB = (LINES + 15) / 16;
-  constexpr int MBLK = DGMG_FDM_MBLK;
   using M = Mfma<T>;
   // the wave index is uniform over the wave: keeping it scalar makes the block
   // loop a scalar loop
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int mb0 = wave; mb0 < MB; mb0 += MBLK * nw) {
-    int base[MBLK], lc[MBLK];
-    bool lv[MBLK], act[MBLK];
+  for (int mb = wave; mb < MB; mb += nw) {
+    const int line = mb * 16 + li;
+    const bool lv = line < LINES;
+    const int lc = imin(line, LINES - 1);
+    const int base = fdm_line_base<NA, NL, TD>(lc);
+    typename M::acc_t acc[NB];
 #pragma unroll
-    for (int t = 0; t < MBLK; ++t) {
-      const int mb = mb0 + t * nw, line = mb * 16 + li;
-      act[t] = mb < MB;  // wave-uniform
-      lv[t] = act[t] && line < LINES;
-      lc[t] = imin(line, LINES - 1);
-      base[t] = fdm_line_base<NA, NL, TD>(lc[t]);
-    }
-    typename M::acc_t acc[MBLK][NB];
-#pragma unroll
-    for (int t = 0; t < MBLK; ++t)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[t][nb] = typename M::acc_t{0, 0, 0, 0};
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < (TAIL ? KS - 1 : KS); ++ks) {
       const int k = imin(4 * ks + lk, LEN - 1);
-      T a[MBLK];
+      const T a = tile[base + k * STRIDE];
 #pragma unroll
-      for (int t = 0; t < MBLK; ++t) a[t] = act[t] ? tile[base[t] + k * STRIDE] : T(0);
-#pragma unroll
-      for (int t = 0; t < MBLK; ++t)
-        if (act[t])
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = M::op(B.b[nb][ks], a[t], acc[t][nb]);
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(B.b[nb][ks], a, acc[nb]);
     }
     if constexpr (TAIL) {
       // LEN = 4 (KS - 1) + 1: the last contraction index is alone in its group
       // of four, so it is added on the VALU as a rank-one update (tail = row
       // LEN - 1 of B in LDS) instead of a fourth product that is 3/4 padding
-#pragma unroll
-      for (int t = 0; t < MBLK; ++t) {
-        const T at = act[t] ? tile[base[t] + (LEN - 1) * STRIDE] : T(0);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int j = imin(nb * 16 + M::row(lk, r), LEN - 1);
-            acc[t][nb][r] = __builtin_fma(tail[j], at, acc[t][nb][r]);
-          }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < MBLK; ++t) {
-      if (!act[t]) continue;
+      const T at = tile[base + (LEN - 1) * STRIDE];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int j = nb * 16 + M::row(lk, r);
-          const bool ok = lv[t] && j < LEN;
-          const int jc = imin(j, LEN - 1);
-          T* dst = ok ? tile + base[t] + jc * STRIDE : trash + lane;
-          *dst = post(lc[t], jc, acc[t][nb][r]);
+          const int j = imin(nb * 16 + M::row(lk, r), LEN - 1);
+          acc[nb][r] = __builtin_fma(tail[j], at, acc[nb][r]);
         }
     }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = nb * 16 + M::row(lk, r);
+        const bool ok = lv && j < LEN;
+        const int jc = imin(j, LEN - 1);
+        T* dst = ok ? tile + base + jc * STRIDE : trash + lane;
+        *dst = post(lc, jc, acc[nb][r]);
+      }
   }
 }
 
@@ -909,14 +878,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
       bwd[t] = dd.ST_ec + (int64_t)p[d] * NL * NL;
     }
   }
-  // small bases (lengths <= 16: four values per lane and pass) are loaded into
-  // registers once, their latency hidden behind the gather
-  constexpr bool PRE = DGMG_FDM_PRELOAD && NA <= 16 && NL <= 16;
-  BOp<T, NA> F0, B0;
-  BOp<T, NL> F1, B1, F2, B2;
   // two operand register sets used in turn (3D, every pass on the matrix cores,
   // both lengths with the same register shape)
-  constexpr bool PING = DGMG_FDM_PING && !PRE && DIM == 3 && NA > DGMG_FDM_VALU_MAXLEN &&
+  constexpr bool PING = DGMG_FDM_PING && DIM == 3 && NA > DGMG_FDM_VALU_MAXLEN &&
                         NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
                         BOp<T, NA>::NB == BOp<T, NL>::NB;
   BOp<T, NA> P, Q;
@@ -932,16 +896,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
       for (int j = tid; j < NL; j += nth) sBt[m][j] = rows[m][(NL - 1) * NL + j];
   }
   if constexpr (PING) P.load(fwd[0]);
-  if constexpr (PRE) {
-    F0.load(fwd[0]);
-    F1.load(fwd[1]);
-    B0.load(bwd[0]);
-    B1.load(bwd[1]);
-    if constexpr (DIM == 3) {
-      F2.load(fwd[2]);
-      B2.load(bwd[2]);
-    }
-  }
   __syncthreads();
   // gather R_s r in grid-natural order (coalesced global reads); GU loads are
   // issued before their LDS stores; positions outside a Dirichlet domain read
@@ -1023,26 +977,24 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
     fdm_pass<T, NA, NL, DIM, 0, NoPost, NA>(tile, trash, Q);
     __syncthreads();
   } else {
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, F0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, fwd[0], bwd[0]);
-  __syncthreads();
-  if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, F1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1]);
+    fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, fwd[0], bwd[0]);
     __syncthreads();
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, trash, F2, scale);
-    else fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, fwd[2], bwd[2], scale);
-  } else {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, F1, scale);
-    else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1], scale);
-  }
-  __syncthreads();
-  if constexpr (DIM == 3) {
-    if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 2>(tile, trash, B2); else fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, bwd[2], fwd[2]);
+    if constexpr (DIM == 3) {
+      fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1]);
+      __syncthreads();
+      fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, fwd[2], bwd[2], scale);
+    } else {
+      fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, fwd[1], bwd[1], scale);
+    }
     __syncthreads();
-  }
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 1>(tile, trash, B1); else fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, bwd[1], fwd[1]);
-  __syncthreads();
-  if constexpr (PRE) fdm_pass<T, NA, NL, DIM, 0>(tile, trash, B0); else fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, bwd[0], fwd[0]);
-  __syncthreads();
+    if constexpr (DIM == 3) {
+      fdm_pass_any<T, NA, NL, DIM, 2>(tile, trash, bwd[2], fwd[2]);
+      __syncthreads();
+    }
+    fdm_pass_any<T, NA, NL, DIM, 1>(tile, trash, bwd[1], fwd[1]);
+    __syncthreads();
+    fdm_pass_any<T, NA, NL, DIM, 0>(tile, trash, bwd[0], fwd[0]);
+    __syncthreads();
   }
   // weighted result w_s (.) Delta u_s in grid-natural order; row weight w1 w2
   const auto row_w = [&](int rw) -> T {
