@@ -18,9 +18,10 @@ Also on the line:
 * smoothing_step: one whole top-level smoothing step against its attainable
   roof max(bytes / HBM peak, flops / compute peak);
 * mixed: the FP32 V-cycle inside FP64 PCG on the same input;
-* c3, c5, c4 (unless --quick): 32^3 LDG stretched to aspect ratio 32, 8^3 at
-  P = 32 (with the learned face weights), and 64 batched grids, each against
-  the plain FP64 solver (one by one for the batch);
+* c3, c5, c4, c4_small (unless --quick): 32^3 LDG stretched to aspect ratio
+  32, 8^3 at P = 32 (with the learned face weights), 64 batched grids, and 64
+  small batched grids, each against the plain FP64 solver (one by one, and one
+  by one in mixed precision, for the batches);
 * cpu_baseline: the oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -309,15 +310,19 @@ def _extra_workload(name, args):
     return out
 
 
-def _batched_entry(args):
-    """64 grids in one batched, graph-replayed MGCG (FP32 V-cycle in FP64 PCG) against
-    the same grids solved one after another, in mixed precision and in FP64."""
+def _batched_entry(args, small=False):
+    """64 grids in one batched MGCG (FP32 V-cycle in FP64 PCG; work-list launches
+    shared by the grids' smaller levels) against the same grids solved one after
+    another, in mixed precision and in FP64.  small: 64 grids of 2^3..6^3
+    elements at P in {4, 6, 8} (seed 40), where every level is small enough to
+    share launches."""
     import numpy as np
     import torch
     import synth
     from paper_1603_02524_amd import dgmg
-    ws = synth.c4_batched()
+    ws = synth.c4_batched(seed=40, n_range=(2, 6), orders=(4, 6, 8)) if small else synth.c4_batched()
     B = dgmg.BatchSolver([(w.grid, w.method) for w in ws], max_iter=200)
+    planned, kernels, grid_ops = B.plan_info()
     n = B.n_dof
     rhs = torch.tensor(np.concatenate([synth.rhs_uniform(w.seed, w.n_dof) for w in ws]), device="cuda")
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -335,10 +340,12 @@ def _batched_entry(args):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     its = [s["iterations"] for s in st]
-    out = {"workload": f"batched_{len(ws)}_grids_3d_mixed", "grids": len(ws), "n_dof": n, "ms_per_step": sec * 1e3,
-           "value": n / sec, "iterations_min_max": [min(its), max(its)],
+    out = {"workload": f"batched_{len(ws)}_{'small_' if small else ''}grids_3d_mixed", "grids": len(ws), "n_dof": n,
+           "ms_per_step": sec * 1e3, "value": n / sec, "iterations_min_max": [min(its), max(its)],
            "converged": all(s["converged"] for s in st),
-           "true_rel_residual_max": max(s["r_true"] / s["r0"] for s in st)}
+           "true_rel_residual_max": max(s["r_true"] / s["r0"] for s in st),
+           "plan": {"work_lists": planned, "batched_launches_per_iteration": kernels,
+                    "per_grid_ops_per_iteration": grid_ops}}
     B.close()
     for prec in ("mixed", "fp64"):
         _log(f"c4: the same grids one by one, {prec}")
@@ -434,6 +441,8 @@ def main():
         out["c5"] = _extra_workload("c5", args)
         _log("c4: batched grids")
         out["c4"] = _batched_entry(args)
+        _log("c4: small batched grids")
+        out["c4_small"] = _batched_entry(args, small=True)
 
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle on a bounded sample")

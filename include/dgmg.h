@@ -272,15 +272,29 @@ const char* dgmg_last_error(const dgmg_handle* h);
 /* ---------------------------------------------------------------- batches
  * Many independent grids (own sizes, orders, options) solved together:
  * MGCG runs in lock step with one host synchronisation per iteration for all
- * grids; each phase of an iteration is one hipGraph whose per-grid chains are
- * independent (captured once, replayed; converged grids are masked by a
- * device flag that every kernel checks).  Vectors of all grids are
+ * grids; converged grids are masked by a device flag that every kernel
+ * checks.  When all grids share the multigrid precision, the smoothing counts
+ * and the V-cycle kind, use additive smoothers and have no 3D P = 32 level,
+ * each phase of an iteration is a work-list plan: every step of every grid's
+ * phase is keyed by its position (the top-level apply; in the V-cycle the
+ * depth below the top level, smoothing step, sweep, sub-step), and the steps
+ * at one position that use the same kernel instance (order, tile, mode) run as
+ * ONE launch over all those grids' elements or patches, with per-grid
+ * argument descriptors in the workspace; vector updates, fills and coarse
+ * solves stay per grid.  Otherwise each grid's chain is issued on its own.
+ * Either way a phase is issued eagerly (the default; the per-grid
+ * operations of converged grids are then left out) or captured once as a
+ * hipGraph and replayed.  Vectors of all grids are
  * concatenated (FP64, element-major per grid) at the offsets reported by
  * dgmg_batch_offsets.  Extension beyond the paper (many-grid throughput). */
 
 /* Set up `count` grids (host work only); grids[i], opts[i] as for dgmg_setup. */
 int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, dgmg_batch** out);
 int dgmg_batch_workspace_bytes(const dgmg_batch* b, size_t* bytes);
+/* The execution plan (host outputs, NULL allowed): planned = 1 when the phases
+ * run as work-list plans; kernels = batched launches per MGCG iteration (both
+ * phases), grid_ops = per-grid operations per iteration. */
+int dgmg_batch_plan_info(const dgmg_batch* b, int* planned, int* kernels, int* grid_ops);
 /* Bind one caller-allocated device workspace (256-byte aligned) for all grids. */
 int dgmg_batch_bind_workspace(dgmg_batch* b, void* dev, size_t bytes, void* stream);
 /* Host array of count + 1 offsets of each grid's unknowns in the concatenation. */
@@ -291,7 +305,8 @@ int dgmg_batch_handle(dgmg_batch* b, int i, dgmg_handle** h);
 /* Autotune every grid's sweeps (shapes with identical tiles and patch counts
  * are timed once). */
 int dgmg_batch_autotune(dgmg_batch* b);
-/* Graph replay on (default) or eager per-grid launches. */
+/* Graph replay of each phase on, or eager launches (the default: an eager
+ * phase leaves out the per-grid operations of converged grids). */
 int dgmg_batch_use_graphs(dgmg_batch* b, int enable);
 /* Solve all grids to ||r_i|| <= tol ||r_i,0|| (each grid's own max_iter);
  * st: host array of count dgmg_stats (may be NULL).  DGMG_NOT_CONVERGED if

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -373,10 +374,27 @@ struct dgmg_batch {
   int* flags_host = nullptr;
   double* rr_host = nullptr;
   bool bound = false;
-  bool use_graphs = true;
+  // graph replay of the phases (off by default: an eager planned phase can
+  // leave out the per-grid operations of converged grids, a recorded one
+  // cannot, and measured faster on the 64-grid workload)
+  bool use_graphs = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   const double* graph_x = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only while capturing
   std::string err;
+  // batched execution plan (see batch_plan): per MGCG phase the launches over
+  // work lists of all grids; descriptors in the workspace at plan_off
+  struct Launch {
+    int kind = 0, dim = 3, f32 = 0, t[4] = {0, 0, 0, 0};
+    int ng = 0, ntot = 0;
+    size_t desc_off = 0, starts_off = 0;
+    std::vector<std::function<int()>> fns;
+    std::vector<int> fn_grid;  // the grid of each of fns
+  };
+  bool planned = false;
+  std::vector<Launch> plan[2];
+  size_t plan_off = 0, plan_bytes = 0;
+  double* x_cur = nullptr;  // the solve's x while a phase is recorded or run
 };
 
 namespace {
@@ -988,12 +1006,19 @@ int pcg_init_b(dgmg_handle* h) {
 }
 
 // q = A p; alpha = delta / p.q; x += alpha p; r_old = r; r -= alpha q; r.r
+int pcg_phase_a_tail(dgmg_handle* h, double* x, int nb);
 int pcg_phase_a(dgmg_handle* h, double* x) {
   const int L = (int)h->lv.size() - 1;
-  const int64_t n = h->lv[L].n_dof;
   int nb = 0;
   int rc = k_apply<double>(h, L, 2, h->pp, nullptr, h->pq, h->part, &nb);
   if (rc) return rc;
+  return pcg_phase_a_tail(h, x, nb);
+}
+
+// Phase a after q = A p (nb partial sums of p.q in part)
+int pcg_phase_a_tail(dgmg_handle* h, double* x, int nb) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VEC_THREADS), 0, h->stream, h->part, nb, h->scal + S_PQ, h->active);
   float* rf = mixed(h) ? (float*)h->buf[L].f : nullptr;  // the next V-cycle's FP32 input
   hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, h->pr, h->pro, h->pp, h->pq,
@@ -1003,6 +1028,7 @@ int pcg_phase_a(dgmg_handle* h, double* x) {
 }
 
 // z = MG(r); beta = z.(r - r_old) / delta; p = z + beta p; delta = z.r
+int pcg_phase_b_tail(dgmg_handle* h);
 int pcg_phase_b(dgmg_handle* h) {
   const int L = (int)h->lv.size() - 1;
   const int64_t n = h->lv[L].n_dof;
@@ -1012,6 +1038,14 @@ int pcg_phase_b(dgmg_handle* h) {
   const bool mx = mixed(h);
   int rc = precond(h, h->pr, h->pz, !mx, !mx);
   if (rc) return rc;
+  return pcg_phase_b_tail(h);
+}
+
+// Phase b after the V-cycle
+int pcg_phase_b_tail(dgmg_handle* h) {
+  const int L = (int)h->lv.size() - 1;
+  const int64_t n = h->lv[L].n_dof;
+  const bool mx = mixed(h);
   const float* zf = (const float*)h->buf[L].u;
   if (mx)
     hipLaunchKernelGGL((k_dot_zr<float>), dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, zf, h->pr, h->pro,
@@ -1796,6 +1830,385 @@ int dgmg_apply_mlp(dgmg_handle* h, const float* params, void* work, size_t bytes
   return DGMG_FELLBACK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------- batched execution plan
+namespace {
+
+// A batch whose grids share the multigrid precision, the smoothing counts and
+// the V-cycle kind, with additive smoothers and no large (3D P = 32) levels,
+// runs each MGCG phase as one list of launches over work lists (BatchList):
+// every step of every grid's phase is keyed by its position (phase a: the
+// top-level apply q = A p; phase b: the V-cycle, steps keyed by depth below the
+// top level, smoothing step, sweep and sub-step), and the steps at one position
+// that use the same kernel instance become one launch over all their grids,
+// one argument descriptor per grid.  Each grid sees the same kernels on the
+// same data in the same order as in its own solve (bitwise the same results).
+// The PCG vector operations, fills and coarse solves stay per grid.
+enum { BK_APPLY = 0, BK_FDM = 1, BK_COMB = 2, BK_XFER = 3, BK_FN = 4 };
+
+struct BStep {
+  std::vector<int> key;
+  int kind = BK_FN, dim = 3, f32 = 0, t[4] = {0, 0, 0, 0};
+  int grid = 0, nblk = 0;
+  std::vector<char> args;
+  std::function<int()> fn;
+};
+
+template <class A>
+std::vector<char> arg_bytes(const A& a) {
+  std::vector<char> v(sizeof(A));
+  std::memcpy(v.data(), &a, sizeof(A));
+  return v;
+}
+
+bool batch_plannable(const dgmg_batch* b) {
+  const dgmg_handle* h0 = b->h[0];
+  for (const dgmg_handle* h : b->h) {
+    if (multiplicative(h)) return false;
+    if (h->opts.precision != h0->opts.precision || h->opts.ns_pre != h0->opts.ns_pre ||
+        h->opts.ns_post != h0->opts.ns_post || h->opts.vcycle != h0->opts.vcycle)
+      return false;
+    for (const LevelHost& lv : h->lv)
+      if (lv.dim == 3 && lv.NP == BIG_NP) return false;
+  }
+  return true;
+}
+
+// Levels with at least this many unknowns fill the GPU alone: their steps keep
+// the single-grid launches (autotuned block shapes, arguments in scalar
+// registers) and only the smaller levels share work-list launches.
+constexpr int64_t SOLO_DOF = 1 << 20;
+
+// Steps of one grid's V-cycle (as k_vcycle, k_smooth, k_sweep,
+// k_residual_restrict and k_transfer issue them).
+template <class T>
+void vcycle_steps(dgmg_handle* h, int gi, const T* r_top, T* z_top, std::vector<BStep>& out) {
+  const int L = (int)h->lv.size() - 1;
+  const int f32 = sizeof(T) == 4;
+  const bool var = h->opts.vcycle == DGMG_VCYCLE_VARIABLE;
+  auto ns = [&](int l, int which) {
+    const int base = which == 0 ? h->opts.ns_pre : h->opts.ns_post;
+    return var ? base << (L - l) : base;
+  };
+  std::vector<T*> u(L + 1), f(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    u[l] = (T*)h->buf[l].u;
+    f[l] = (T*)h->buf[l].f;
+  }
+  u[L] = z_top;
+  f[L] = const_cast<T*>(r_top);
+  T* patch = (T*)h->patch;
+  auto step = [&](std::vector<int> key, int kind, int dim, std::initializer_list<int> t, int nblk,
+                  std::vector<char> args) {
+    BStep st;
+    st.key = std::move(key);
+    st.kind = kind;
+    st.dim = dim;
+    st.f32 = f32;
+    int k = 0;
+    for (int v : t) st.t[k++] = v;
+    st.grid = gi;
+    st.nblk = nblk;
+    st.args = std::move(args);
+    out.push_back(std::move(st));
+  };
+  auto fnstep = [&](std::vector<int> key, std::function<int()> fn) {
+    BStep st;
+    st.key = std::move(key);
+    st.kind = BK_FN;
+    st.grid = gi;
+    st.fn = std::move(fn);
+    out.push_back(std::move(st));
+  };
+  auto blocks_apply = [&](const LevelDev<T>& Lv) {
+    return Lv.dim == 3 ? Kern<T, 3>::apply_blocks_of(Lv.NP, Lv.n_elem) : Kern<T, 2>::apply_blocks_of(Lv.NP, Lv.n_elem);
+  };
+  auto apply_args = [&](const LevelDev<T>& Lv, const T* x, const T* fv, T* y) {
+    ApplyArgs<T> a;
+    a.L = Lv;
+    a.x = x;
+    a.f = fv;
+    a.y = y;
+    a.nblk = blocks_apply(Lv);
+    return a;
+  };
+  // one smoothing call: steps s, sweeps i (EA: one, FA: one per direction);
+  // keys {major, depthkey, s, i, sub-step}
+  auto smooth = [&](int major, int depthkey, int l, int steps, bool u_zero) {
+    const LevelDev<T>& Lv = LD<T>(h, l);
+    const LevelHost& lv = h->lv[l];
+    T* rl = (T*)h->buf[l].r;
+    const int nsw = ec_smoother(h) ? 1 : lv.dim;
+    const bool solo = lv.n_dof >= SOLO_DOF;
+    for (int s = 0; s < steps; ++s)
+      for (int i = 0; i < nsw; ++i) {
+        const int nd = ec_smoother(h) ? -1 : i;
+        const bool uz = u_zero && s == 0 && i == 0;
+        if (solo) {
+          T* ul = u[l];
+          const T* fl = f[l];
+          fnstep({major, depthkey, s, i, 0}, [h, l, nd, ul, fl, rl, uz]() { return k_sweep<T>(h, l, nd, ul, fl, rl, uz); });
+          continue;
+        }
+        if (!uz) {
+          ApplyArgs<T> a = apply_args(Lv, u[l], f[l], rl);
+          step({major, depthkey, s, i, 0}, BK_APPLY, lv.dim, {lv.NP, 1}, a.nblk, arg_bytes(a));
+        }
+        int np[3], NA, NL;
+        sweep_shape(lv, nd, np, NA, NL);
+        FdmArgs<T> fa;
+        fa.L = Lv;
+        fa.r = uz ? f[l] : rl;
+        fa.out = patch;
+        fa.npx = np[0];
+        fa.npy = np[1];
+        fa.npz = np[2];
+        step({major, depthkey, s, i, 1}, BK_FDM, lv.dim, {nd, NA, NL}, np[0] * np[1] * np[2], arg_bytes(fa));
+        CombArgs<T> ca;
+        ca.L = Lv;
+        ca.buf = patch;
+        ca.u = u[l];
+        ca.nd = nd;
+        ca.NA = NA;
+        ca.NL = NL;
+        ca.npx = np[0];
+        ca.npy = np[1];
+        ca.npz = np[2];
+        ca.nblk = lv.dim == 3 ? Kern<T, 3>::combine_blocks_of(lv.NP, lv.n_elem)
+                              : Kern<T, 2>::combine_blocks_of(lv.NP, lv.n_elem);
+        ca.assign = uz ? 1 : 0;
+        step({major, depthkey, s, i, 2}, BK_COMB, lv.dim, {lv.NP, combine_maxc(lv.NP, lv.NO)}, ca.nblk,
+             arg_bytes(ca));
+      }
+  };
+  auto xfer_args = [&](const LevelDev<T>& Lv, const T* in, T* o) {
+    XferArgs<T> a;
+    a.J = Lv.J;
+    a.n_elem = Lv.n_elem;
+    a.in = in;
+    a.out = o;
+    a.active = Lv.active;
+    return a;
+  };
+  auto xfer_blocks = [&](const LevelDev<T>& Lv) {
+    return Lv.dim == 3 ? Kern<T, 3>::xfer_blocks_of(Lv.NP, Lv.n_elem) : Kern<T, 2>::xfer_blocks_of(Lv.NP, Lv.n_elem);
+  };
+  for (int l = L; l >= 1; --l) {
+    const int k = L - l;
+    const bool pre = ns(l, 0) > 0;
+    if (!pre) {
+      T* ul = u[l];
+      const int64_t n = h->lv[l].n_dof;
+      fnstep({1, k, -1, 0, 0}, [h, ul, n]() {
+        k_fill_v<T>(h, ul, n);
+        return check_hip(h, "fill");
+      });
+    }
+    smooth(1, k, l, ns(l, 0), pre);
+    const LevelDev<T>& Lv = LD<T>(h, l);
+    const LevelHost& lv = h->lv[l];
+    // the fused form where built; the structure only depends on the orders
+    // (J is null in a dry run before the workspace is bound)
+    LevelDev<T> probe = Lv;
+    if (!probe.J) probe.J = (const T*)&probe;
+    const bool m3 = h->fuse_restrict &&
+                    (lv.dim == 3 ? Kern<T, 3>::mode3_ok(probe) : Kern<T, 2>::mode3_ok(probe));
+    T* rl = (T*)h->buf[l].r;
+    if (lv.n_dof >= SOLO_DOF) {
+      T* ul = u[l];
+      const T* fl = f[l];
+      T* fc = f[l - 1];
+      fnstep({1, k, 1000, 0, 0}, [h, l, ul, fl, rl, fc]() { return k_residual_restrict<T>(h, l, ul, fl, rl, fc); });
+    } else if (m3) {
+      ApplyArgs<T> a = apply_args(Lv, u[l], f[l], f[l - 1]);
+      step({1, k, 1000, 0, 0}, BK_APPLY, lv.dim, {lv.NP, 3}, a.nblk, arg_bytes(a));
+    } else {
+      ApplyArgs<T> a = apply_args(Lv, u[l], f[l], rl);
+      step({1, k, 1000, 0, 0}, BK_APPLY, lv.dim, {lv.NP, 1}, a.nblk, arg_bytes(a));
+      XferArgs<T> x = xfer_args(Lv, rl, f[l - 1]);
+      step({1, k, 1000, 0, 1}, BK_XFER, lv.dim, {lv.NP, lv.NPc, 1}, xfer_blocks(Lv), arg_bytes(x));
+    }
+  }
+  {
+    T* f0 = f[0];
+    T* u0 = u[0];
+    fnstep({2}, [h, f0, u0]() { return k_coarse<T>(h, f0, u0); });
+  }
+  for (int l = 1; l <= L; ++l) {
+    const int k = L - l;
+    const LevelDev<T>& Lv = LD<T>(h, l);
+    const LevelHost& lv = h->lv[l];
+    if (lv.n_dof >= SOLO_DOF) {
+      const T* uc = u[l - 1];
+      T* ul = u[l];
+      fnstep({3, -k, -1, 0, 0}, [h, l, uc, ul]() { return k_transfer<T>(h, l, false, uc, ul); });
+    } else {
+      XferArgs<T> x = xfer_args(Lv, u[l - 1], u[l]);
+      step({3, -k, -1, 0, 0}, BK_XFER, lv.dim, {lv.NP, lv.NPc, 0}, xfer_blocks(Lv), arg_bytes(x));
+    }
+    smooth(3, -k, l, ns(l, 1), false);
+  }
+}
+
+// Steps of both MGCG phases of every grid, merged into launches.  fill = false:
+// a dry run (before the workspace is bound) that only sizes the descriptors.
+int batch_plan(dgmg_batch* b, bool fill) {
+  b->plan[0].clear();
+  b->plan[1].clear();
+  b->planned = batch_plannable(b);
+  if (!b->planned) {
+    b->plan_bytes = 0;
+    return DGMG_OK;
+  }
+  std::vector<BStep> steps[2];
+  const int n = (int)b->h.size();
+  for (int gi = 0; gi < n; ++gi) {
+    dgmg_handle* h = b->h[gi];
+    const int L = (int)h->lv.size() - 1;
+    // phase a: q = A p (top level, FP64), then the grid's own updates
+    const LevelDev<double>& Lt = h->Ld[L];
+    if (h->lv[L].n_dof >= SOLO_DOF) {
+      BStep st;
+      st.key = {0};
+      st.grid = gi;
+      const int64_t off = b->dof_off[gi];
+      st.fn = [b, h, off]() { return pcg_phase_a(h, b->x_cur + off); };
+      steps[0].push_back(std::move(st));
+    } else {
+    ApplyArgs<double> a;
+    a.L = Lt;
+    a.x = h->pp;
+    a.y = h->pq;
+    a.part = h->part;
+    a.nblk = Lt.dim == 3 ? Kern<double, 3>::apply_blocks_of(Lt.NP, Lt.n_elem)
+                         : Kern<double, 2>::apply_blocks_of(Lt.NP, Lt.n_elem);
+    BStep st;
+    st.key = {0};
+    st.kind = BK_APPLY;
+    st.dim = Lt.dim;
+    st.f32 = 0;
+    st.t[0] = Lt.NP;
+    st.t[1] = 2;
+    st.grid = gi;
+    st.nblk = a.nblk;
+    st.args = arg_bytes(a);
+    steps[0].push_back(std::move(st));
+    BStep tail;
+    tail.key = {1};
+    tail.grid = gi;
+    const int nb = a.nblk;
+    const int64_t off = b->dof_off[gi];
+    tail.fn = [b, h, nb, off]() { return pcg_phase_a_tail(h, b->x_cur + off, nb); };
+    steps[0].push_back(std::move(tail));
+    }
+    // phase b: the V-cycle (mixed: on the FP32 copies of r and z), then the direction update
+    if (mixed(h)) vcycle_steps<float>(h, gi, (const float*)h->buf[L].f, (float*)h->buf[L].u, steps[1]);
+    else vcycle_steps<double>(h, gi, h->pr, h->pz, steps[1]);
+    BStep tb;
+    tb.key = {9};
+    tb.grid = gi;
+    tb.fn = [h]() { return pcg_phase_b_tail(h); };
+    steps[1].push_back(std::move(tb));
+  }
+  std::vector<char> host;
+  auto alloc = [&](size_t bytes) {
+    size_t o = (host.size() + 255) & ~size_t(255);
+    host.resize(o + bytes);
+    return o;
+  };
+  for (int ph = 0; ph < 2; ++ph) {
+    auto& v = steps[ph];
+    auto sig = [](const BStep& s) { return std::make_tuple(s.kind, s.dim, s.f32, s.t[0], s.t[1], s.t[2], s.t[3]); };
+    std::stable_sort(v.begin(), v.end(), [&](const BStep& x, const BStep& y) {
+      if (x.key != y.key) return x.key < y.key;
+      if (sig(x) != sig(y)) return sig(x) < sig(y);
+      return x.grid < y.grid;
+    });
+    for (size_t i = 0; i < v.size();) {
+      size_t j = i + 1;
+      while (j < v.size() && v[j].key == v[i].key && sig(v[j]) == sig(v[i])) ++j;
+      dgmg_batch::Launch ln;
+      ln.kind = v[i].kind;
+      ln.dim = v[i].dim;
+      ln.f32 = v[i].f32;
+      for (int k = 0; k < 4; ++k) ln.t[k] = v[i].t[k];
+      ln.ng = (int)(j - i);
+      if (ln.kind == BK_FN) {
+        for (size_t k = i; k < j; ++k) {
+          ln.fns.push_back(v[k].fn);
+          ln.fn_grid.push_back(v[k].grid);
+        }
+      } else {
+        const size_t asz = v[i].args.size();
+        ln.desc_off = alloc(asz * ln.ng);
+        for (size_t k = i; k < j; ++k) std::memcpy(host.data() + ln.desc_off + (k - i) * asz, v[k].args.data(), asz);
+        ln.starts_off = alloc(sizeof(int) * (ln.ng + 1));
+        int* st = (int*)(host.data() + ln.starts_off);
+        st[0] = 0;
+        for (size_t k = i; k < j; ++k) st[k - i + 1] = st[k - i] + v[k].nblk;
+        ln.ntot = st[ln.ng];
+      }
+      b->plan[ph].push_back(std::move(ln));
+      i = j;
+    }
+  }
+  if (!fill) {
+    b->plan_bytes = host.size() + 256;
+    return DGMG_OK;
+  }
+  if (host.size() > b->plan_bytes) return DGMG_EINVAL;  // the dry run sized the region
+  hipError_t e = hipMemcpyAsync(b->ws + b->plan_off, host.data(), host.size(), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? DGMG_OK : DGMG_EHIP;
+}
+
+template <class A>
+BatchList<A> blist(dgmg_batch* b, const dgmg_batch::Launch& ln) {
+  BatchList<A> bl;
+  bl.descs = (const A*)(b->ws + b->plan_off + ln.desc_off);
+  bl.starts = (const int*)(b->ws + b->plan_off + ln.starts_off);
+  bl.ng = ln.ng;
+  return bl;
+}
+
+template <class T, int DIM>
+int run_launch_t(dgmg_batch* b, const dgmg_batch::Launch& ln, hipStream_t s) {
+  switch (ln.kind) {
+    case BK_APPLY: return Kern<T, DIM>::apply_batch(ln.t[0], ln.t[1], blist<ApplyArgs<T>>(b, ln), ln.ntot, s);
+    case BK_FDM: return Kern<T, DIM>::fdm_batch(ln.t[0], ln.t[1], ln.t[2], blist<FdmArgs<T>>(b, ln), ln.ntot, 0, s);
+    case BK_COMB: return Kern<T, DIM>::combine_batch(ln.t[0], ln.t[1], blist<CombArgs<T>>(b, ln), ln.ntot, s);
+    case BK_XFER:
+      return Kern<T, DIM>::transfer_batch(ln.t[0], ln.t[1], ln.t[2] != 0, blist<XferArgs<T>>(b, ln), ln.ntot, s);
+    default: return -4;
+  }
+}
+
+// skip_done: leave out the per-grid operations of grids that have converged
+// (eager runs; a recorded graph keeps them, and their kernels return at once)
+int run_plan(dgmg_batch* b, int which, hipStream_t s, bool skip_done) {
+  for (const auto& ln : b->plan[which]) {
+    int rc;
+    if (ln.kind == BK_FN) {
+      for (size_t k = 0; k < ln.fns.size(); ++k) {
+        if (skip_done && !b->flags_host[ln.fn_grid[k]]) continue;
+        if ((rc = ln.fns[k]())) return rc;
+      }
+      continue;
+    }
+    if (ln.f32) rc = ln.dim == 3 ? run_launch_t<float, 3>(b, ln, s) : run_launch_t<float, 2>(b, ln, s);
+    else rc = ln.dim == 3 ? run_launch_t<double, 3>(b, ln, s) : run_launch_t<double, 2>(b, ln, s);
+    if (rc) return DGMG_EUNSUPPORTED;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return DGMG_EHIP;
+  }
+  return DGMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 // ------------------------------------------------------------------- batches
 int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, dgmg_batch** out) {
   if (!out || count < 1 || !grids || !opts) return fail(nullptr, DGMG_EINVAL, "bad batch arguments");
@@ -1820,8 +2233,29 @@ int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, d
     cv.off += h->ws_need;
     b->dof_off.push_back(b->dof_off.back() + h->lv.back().n_dof);
   }
+  // the batched execution plan's descriptors (sized by a dry run)
+  batch_plan(b, false);
+  if (b->planned) {
+    cv.off = (cv.off + 255) & ~size_t(255);
+    b->plan_off = cv.off;
+    cv.off += b->plan_bytes;
+  }
   b->ws_need = cv.off + 256;
   *out = b;
+  return DGMG_OK;
+}
+
+int dgmg_batch_plan_info(const dgmg_batch* b, int* planned, int* kernels, int* grid_ops) {
+  if (!b) return DGMG_EINVAL;
+  int k = 0, g = 0;
+  for (const auto& ph : b->plan)
+    for (const auto& ln : ph) {
+      if (ln.kind == BK_FN) g += (int)ln.fns.size();
+      else ++k;
+    }
+  if (planned) *planned = b->planned ? 1 : 0;
+  if (kernels) *kernels = k;
+  if (grid_ops) *grid_ops = g;
   return DGMG_OK;
 }
 
@@ -1885,6 +2319,17 @@ int dgmg_batch_bind_workspace(dgmg_batch* b, void* dev, size_t bytes, void* stre
     int rc = bind_batch_member(b->h[i], b->ws + b->sub_off[i], b->stream, b->flags_dev + i, b->rr_dev + i);
     if (rc) {
       b->err = "grid " + std::to_string(i) + ": " + b->h[i]->err;
+      return rc;
+    }
+  }
+  if (b->planned) {
+    if (b->plan_off < prev_end || b->plan_off + b->plan_bytes > b->ws_need) {
+      b->err = "internal: batch plan region is inconsistent";
+      return DGMG_EINVAL;
+    }
+    int rc = batch_plan(b, true);
+    if (rc) {
+      b->err = "batch plan upload failed";
       return rc;
     }
   }
@@ -1997,8 +2442,47 @@ int dgmg_batch_use_graphs(dgmg_batch* b, int enable) {
 // One MGCG phase for every grid: a graph whose per-grid chains are independent
 // child graphs (captured once, replayed each iteration; converged grids are
 // masked by their device flag), or eager launches.
+// The planned phase (launches over work lists), recorded into one graph per
+// phase and x, or run directly.
+static int batch_phase_planned(dgmg_batch* b, int which, double* x) {
+  b->x_cur = x;
+  if (!b->use_graphs) {
+    int rc = run_plan(b, which, b->stream, true);
+    return rc ? batch_fail(b, rc, "batched launch failed") : DGMG_OK;
+  }
+  if (which == 0 && b->gexec[0] && b->graph_x != x) {
+    (void)hipGraphExecDestroy(b->gexec[0]);
+    b->gexec[0] = nullptr;
+  }
+  if (!b->gexec[which]) {
+    if (!b->cap_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, std::string("capture stream: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+    for (auto* h : b->h) h->stream = b->cap_stream;
+    int rc = run_plan(b, which, b->cap_stream, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    for (auto* h : b->h) h->stream = b->stream;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return batch_fail(b, rc, "batched launch failed");
+    }
+    if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, std::string("end capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec[which], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return batch_fail(b, DGMG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (which == 0) b->graph_x = x;
+  }
+  hipError_t e = hipGraphLaunch(b->gexec[which], b->stream);
+  return e == hipSuccess ? DGMG_OK : batch_fail(b, DGMG_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
 static int batch_phase(dgmg_batch* b, int which, double* x) {
   const int n = (int)b->h.size();
+  if (b->planned) return batch_phase_planned(b, which, x);
   if (!b->use_graphs) {
     for (int i = 0; i < n; ++i) {
       int rc = which == 0 ? pcg_phase_a(b->h[i], x + b->dof_off[i]) : pcg_phase_b(b->h[i]);
@@ -2136,6 +2620,7 @@ void dgmg_batch_destroy(dgmg_batch* b) {
   for (auto& g : b->gexec)
     if (g) (void)hipGraphExecDestroy(g);
   for (auto* h : b->h) dgmg_destroy(h);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->flags_host) (void)hipHostFree(b->flags_host);
   if (b->rr_host) (void)hipHostFree(b->rr_host);
   delete b;

@@ -80,6 +80,106 @@ int Kern<T, DIM>::mult_update(const LevelDev<T>& L, int nd, int NA, int NL, cons
 }
 
 template <class T, int DIM>
+int Kern<T, DIM>::apply_blocks_of(int NP, int n_elem) {
+  switch (NP) {
+#define DGMG_CASE(N) \
+  case N: return (DIM == 3 && N == BIG_NP) ? -4 : apply_blocks<DIM, N>(n_elem);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::combine_blocks_of(int NP, int n_elem) {
+  switch (NP) {
+#define DGMG_CASE(N) \
+  case N: return combine_blocks<DIM, N>(n_elem);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::xfer_blocks_of(int NPF, int n_elem) {
+  switch (NPF) {
+#define DGMG_CASE(N) \
+  case N: return (DIM == 3 && N == BIG_NP) ? -4 : xfer_blocks<DIM, N>(n_elem);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+bool Kern<T, DIM>::mode3_ok(const LevelDev<T>& L) {
+  switch (L.NP) {
+#define DGMG_CASE(N) \
+  case N: return apply_mode3_ok<T, DIM, N>(L);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return false;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::apply_batch(int NP, int mode, const BatchList<ApplyArgs<T>>& bl, int ntot, hipStream_t s) {
+  switch (NP) {
+#define DGMG_CASE(N)                                                   \
+  case N:                                                              \
+    if constexpr (DIM == 3 && N == BIG_NP)                             \
+      return -4;                                                       \
+    else                                                               \
+      return apply_batch_launch<T, DIM, N>(mode, bl, ntot, s);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::fdm_batch(int nd, int NA, int NL, const BatchList<FdmArgs<T>>& bl, int ntot, int waves,
+                            hipStream_t s) {
+#define DGMG_CASE(A, B)                                                          \
+  if (NA == A && NL == B) {                                                      \
+    if constexpr (DIM == 3 && fdm_lds_total<T, A, B, DIM>() > LDS_BYTES)         \
+      return -4;                                                                 \
+    else                                                                         \
+      return fdm_batch_launch<T, DIM, A, B>(nd, bl, ntot, waves, s);             \
+  }
+  DGMG_FDM_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return -4;
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::combine_batch(int NP, int maxc, const BatchList<CombArgs<T>>& bl, int ntot, hipStream_t s) {
+  switch (NP) {
+#define DGMG_CASE(N) \
+  case N: return combine_batch_launch<T, DIM, N>(maxc, bl, ntot, s);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::transfer_batch(int NPF, int NPC, bool restrict_, const BatchList<XferArgs<T>>& bl, int ntot,
+                                 hipStream_t s) {
+#define DGMG_CASE(F, C)                                                        \
+  if (NPF == F && NPC == C) {                                                  \
+    if constexpr (DIM == 3 && F == BIG_NP)                                     \
+      return -4;                                                               \
+    else                                                                       \
+      return transfer_batch_launch<T, DIM, F, C>(restrict_, bl, ntot, s);      \
+  }
+  DGMG_XFER_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return -4;
+}
+
+template <class T, int DIM>
 int Kern<T, DIM>::combine(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                           int npy, int npz, bool assign, hipStream_t s) {
   switch (L.NP) {

@@ -74,6 +74,41 @@ struct PatchLat {
   int stride[3] = {1, 1, 1};
 };
 
+// Work list of a batched launch: one kernel over the work of many grids.  The
+// launch's logical blocks are split into consecutive ranges, range g
+// (starts[g] <= b < starts[g + 1], g < ng) doing grid g's blocks with the
+// arguments descs[g] (device arrays; the grid index is uniform per block, so
+// these reads are scalar loads).
+template <class A>
+struct BatchList {
+  const A* descs = nullptr;
+  const int* starts = nullptr;
+  int ng = 0;
+};
+
+// Arguments of logical block b of a batched launch, copied into the block's
+// LDS slot `args` (the kernels index their argument structs with run-time
+// direction indices: from LDS that stays a plain LDS read, from a local copy it
+// would go through scratch memory); returns the block's index within its grid.
+// Called by every thread of the block.
+template <class A>
+__device__ __forceinline__ int batch_pick(const BatchList<A>& bl, int b, A* args) {
+  static_assert(sizeof(A) % sizeof(int) == 0, "argument struct of whole words");
+  const int* __restrict__ st = bl.starts;
+  int lo = 0, hi = bl.ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const int* __restrict__ src = reinterpret_cast<const int*>(bl.descs + lo);
+  int* dst = reinterpret_cast<int*>(args);
+  for (int i = threadIdx.x; i < (int)(sizeof(A) / sizeof(int)); i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return b - st[lo];
+}
+
 // ---------------------------------------------------------------- block reduction
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -184,10 +219,19 @@ template <class T, int DIM, int NIN, int NOUT, int NEF, int D, bool RESTRICT, in
 __device__ __forceinline__ void xfer_pass(const T* __restrict__ sJ, const T* __restrict__ src,
                                           T* __restrict__ dst, int ne);
 
-template <class T, int DIM, int NP, int MODE>
-__global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __restrict__ x,
-                                                     const T* __restrict__ f, T* __restrict__ y,
-                                                     double* __restrict__ part, int nblk) {
+template <class T>
+struct ApplyArgs {
+  LevelDev<T> L;
+  const T* x = nullptr;
+  const T* f = nullptr;
+  T* y = nullptr;
+  double* part = nullptr;
+  int nblk = 0;
+};
+
+// BATCH: the arguments come from the work list bl (ntot logical blocks in all)
+template <class T, int DIM, int NP, int MODE, bool BATCH = false>
+__global__ void __launch_bounds__(1024) apply_kernel(ApplyArgs<T> a0, BatchList<ApplyArgs<T>> bl, int ntot) {
   constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = apply_epb<NP, DIM>();
   constexpr int P = NP - 1;
   constexpr bool STAGE = apply_stage_own<NP, DIM>();
@@ -196,8 +240,26 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   T* sy = reinterpret_cast<T*>(smem_raw);
   T* sx = sy + DIM * EPB * NE;
   __shared__ double red[16];
-  const int blk = xcd_block(nblk);
-  if (blk < 0 || inactive(L.active)) return;
+  __shared__ __align__(16) int sargs_raw[BATCH ? sizeof(ApplyArgs<T>) / sizeof(int) : 1];
+  ApplyArgs<T>* sargs = reinterpret_cast<ApplyArgs<T>*>(sargs_raw);
+  const ApplyArgs<T>* ap;
+  int blk;
+  if constexpr (BATCH) {
+    const int b = xcd_block(ntot);
+    if (b < 0) return;
+    blk = batch_pick(bl, b, sargs);
+    ap = sargs;
+  } else {
+    blk = xcd_block(a0.nblk);
+    if (blk < 0) return;
+    ap = &a0;
+  }
+  const LevelDev<T>& L = ap->L;
+  const T* __restrict__ x = ap->x;
+  const T* __restrict__ f = ap->f;
+  T* __restrict__ y = ap->y;
+  double* __restrict__ part = ap->part;
+  if (inactive(L.active)) return;
   const int e0 = blk * EPB;
   const int ne = imin(EPB, L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -451,36 +513,63 @@ __global__ void __launch_bounds__(1024) apply_kernel(LevelDev<T> L, const T* __r
   }
 }
 
+template <class T, int DIM, int NP, int MODE, bool BATCH>
+void apply_go(const ApplyArgs<T>& a, const BatchList<ApplyArgs<T>>& bl, int nlog, hipStream_t s) {
+  constexpr int TH = apply_threads<NP, DIM>();
+  const size_t shm = apply_shmem<T, DIM, NP>();
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, MODE, BATCH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((apply_kernel<T, DIM, NP, MODE, BATCH>), dim3(xcd_grid(nlog)), dim3(TH), shm, s, a, bl, nlog);
+}
+
+// Blocks of one grid's apply: groups of apply_epb elements.
+template <int DIM, int NP>
+int apply_blocks(int n_elem) {
+  constexpr int EPB = apply_epb<NP, DIM>();
+  return (n_elem + EPB - 1) / EPB;
+}
+
+// The fused residual + restriction (mode 3) is built where the own elements are
+// staged in LDS and the coarse level's order follows P_c = floor(P / 2).
+template <class T, int DIM, int NP>
+bool apply_mode3_ok(const LevelDev<T>& L) {
+  if constexpr (apply_stage_own<NP, DIM>()) return L.NPc == (NP - 1) / 2 + 1 && L.J != nullptr;
+  return false;
+}
+
+template <class T, int DIM, int NP, bool BATCH>
+int apply_mode(int mode, const ApplyArgs<T>& a, const BatchList<ApplyArgs<T>>& bl, int nlog, hipStream_t s) {
+  if (mode == 0) apply_go<T, DIM, NP, 0, BATCH>(a, bl, nlog, s);
+  else if (mode == 1) apply_go<T, DIM, NP, 1, BATCH>(a, bl, nlog, s);
+  else if (mode == 2) apply_go<T, DIM, NP, 2, BATCH>(a, bl, nlog, s);
+  else if constexpr (apply_stage_own<NP, DIM>()) apply_go<T, DIM, NP, 3, BATCH>(a, bl, nlog, s);
+  else return -4;
+  return 0;
+}
+
 template <class T, int DIM, int NP>
 int apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, double* part,
                  int* nblk_out, hipStream_t s) {
-  constexpr int NE = ipow(NP, DIM), EPB = apply_epb<NP, DIM>(), TH = apply_threads<NP, DIM>();
-  const int nblk = (L.n_elem + EPB - 1) / EPB;
+  const int nblk = apply_blocks<DIM, NP>(L.n_elem);
   if (nblk_out) *nblk_out = nblk;
-  dim3 grid(xcd_grid(nblk)), block(TH);
-  const size_t shm = apply_shmem<T, DIM, NP>();
-  if (mode == 0) {
-    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 0>), grid, block, shm, s, L, x, f, y, part, nblk);
-  } else if (mode == 1) {
-    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 1>), grid, block, shm, s, L, x, f, y, part, nblk);
-  } else if (mode == 2) {
-    if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 2>), grid, block, shm, s, L, x, f, y, part, nblk);
-  } else {
-    // fused residual + restriction: own elements staged in LDS and the coarse
-    // level's order following P_c = floor(P / 2); otherwise the caller runs the
-    // two steps
-    if constexpr (apply_stage_own<NP, DIM>()) {
-      if (L.NPc != (NP - 1) / 2 + 1 || !L.J) return -4;
-      if (shm > 65536) (void)hipFuncSetAttribute((const void*)apply_kernel<T, DIM, NP, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((apply_kernel<T, DIM, NP, 3>), grid, block, shm, s, L, x, f, y, part, nblk);
-    } else {
-      return -4;
-    }
-  }
-  return 0;
+  // fused residual + restriction: otherwise the caller runs the two steps
+  if (mode == 3 && !apply_mode3_ok<T, DIM, NP>(L)) return -4;
+  ApplyArgs<T> a;
+  a.L = L;
+  a.x = x;
+  a.f = f;
+  a.y = y;
+  a.part = part;
+  a.nblk = nblk;
+  return apply_mode<T, DIM, NP, false>(mode, a, BatchList<ApplyArgs<T>>{}, nblk, s);
+}
+
+// One launch over the applies of many grids (same NP and mode): ntot logical
+// blocks, grid g's apply_blocks in the range of bl.
+template <class T, int DIM, int NP>
+int apply_batch_launch(int mode, const BatchList<ApplyArgs<T>>& bl, int ntot, hipStream_t s) {
+  return apply_mode<T, DIM, NP, true>(mode, ApplyArgs<T>{}, bl, ntot, s);
 }
 
 // ================================================================ FDM patch solve
@@ -813,9 +902,18 @@ template <int NA, int NL>
 constexpr int fdm_min_waves() {
   return NA == 16 && NL == 13 ? 6 : 1;
 }
-template <class T, int DIM, int NA, int NL, int ND>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_min_waves<NA, NL>()))) fdm_kernel(LevelDev<T> L, const T* __restrict__ r, T* __restrict__ out,
-                                                  int npx, int npy, int npz, PatchLat lat) {
+template <class T>
+struct FdmArgs {
+  LevelDev<T> L;
+  const T* r = nullptr;  // residual (level vector)
+  T* out = nullptr;      // weighted corrections, one tile per patch of the launch
+  int npx = 1, npy = 1, npz = 1;
+  PatchLat lat;
+};
+
+// BATCH: the arguments come from the work list bl (ntot logical blocks in all)
+template <class T, int DIM, int NA, int NL, int ND, bool BATCH = false>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_min_waves<NA, NL>()))) fdm_kernel(FdmArgs<T> a0, BatchList<FdmArgs<T>> bl, int ntot) {
   using S = FdmShape<DIM, ND, NA, NL>;
   constexpr int TS = S::TS;
   constexpr int NMAX = imax(NA, NL);
@@ -829,9 +927,26 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
   // their store trash (64 values)
   __shared__ __align__(8) int rowoff[imax(S::NROW, 64 * (int)sizeof(T) / (int)sizeof(int))];
   __shared__ int rowpos[S::NROW];
-  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
-  const int pid = xcd_block(npatch);
-  if (pid < 0 || inactive(L.active)) return;
+  __shared__ __align__(16) int sargs_raw[BATCH ? sizeof(FdmArgs<T>) / sizeof(int) : 1];
+  FdmArgs<T>* sargs = reinterpret_cast<FdmArgs<T>*>(sargs_raw);
+  const FdmArgs<T>* ap;
+  int pid;
+  if constexpr (BATCH) {
+    const int b = xcd_block(ntot);
+    if (b < 0) return;
+    pid = batch_pick(bl, b, sargs);
+    ap = sargs;
+  } else {
+    pid = xcd_block(a0.npx * a0.npy * (DIM == 3 ? a0.npz : 1));
+    if (pid < 0) return;
+    ap = &a0;
+  }
+  const LevelDev<T>& L = ap->L;
+  const T* __restrict__ r = ap->r;
+  T* __restrict__ out = ap->out;
+  const int npx = ap->npx, npy = ap->npy;
+  const PatchLat& lat = ap->lat;
+  if (inactive(L.active)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   int p[3];
   p[0] = lat.start[0] + lat.stride[0] * (pid % npx);
@@ -1017,35 +1132,54 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
   }
 }
 
-template <class T, int DIM, int NA, int NL, int ND>
-void fdm_launch_nd(const LevelDev<T>& L, const T* r, T* out, int npx, int npy, int npz, int th, size_t shm,
-                   const PatchLat& lat, hipStream_t s) {
-  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+template <class T, int DIM, int NA, int NL, int ND, bool BATCH>
+void fdm_launch_nd(const FdmArgs<T>& a, const BatchList<FdmArgs<T>>& bl, int nlog, int th, size_t shm,
+                   hipStream_t s) {
   if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL, ND>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shm);
-  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL, ND>), dim3(xcd_grid(npatch)), dim3(th), shm, s, L, r, out, npx, npy,
-                     npz, lat);
+    (void)hipFuncSetAttribute((const void*)fdm_kernel<T, DIM, NA, NL, ND, BATCH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((fdm_kernel<T, DIM, NA, NL, ND, BATCH>), dim3(xcd_grid(nlog)), dim3(th), shm, s, a, bl, nlog);
 }
 
 // waves: wavefronts per block (1 .. 8; 0 = default), the shape the autotuner picks.
-template <class T, int DIM, int NA, int NL>
-int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
-                 int waves, const PatchLat& lat, hipStream_t s) {
+template <class T, int DIM, int NA, int NL, bool BATCH>
+int fdm_go(int nd, const FdmArgs<T>& a, const BatchList<FdmArgs<T>>& bl, int nlog, int waves, hipStream_t s) {
   constexpr size_t shm = fdm_shmem<T, NA, NL, DIM>();
   const int th = (waves >= 1 && waves <= 8) ? 64 * waves : fdm_threads<NA, NL, DIM>();
   if (nd < 0) {
     if constexpr (NA == NL) {
-      fdm_launch_nd<T, DIM, NA, NL, -1>(L, r, out, npx, npy, npz, th, shm, lat, s);
+      fdm_launch_nd<T, DIM, NA, NL, -1, BATCH>(a, bl, nlog, th, shm, s);
       return 0;
     }
     return -4;
   }
-  if (nd == 0) fdm_launch_nd<T, DIM, NA, NL, 0>(L, r, out, npx, npy, npz, th, shm, lat, s);
-  else if (nd == 1) fdm_launch_nd<T, DIM, NA, NL, 1>(L, r, out, npx, npy, npz, th, shm, lat, s);
-  else if constexpr (DIM == 3) fdm_launch_nd<T, DIM, NA, NL, 2>(L, r, out, npx, npy, npz, th, shm, lat, s);
+  if (nd == 0) fdm_launch_nd<T, DIM, NA, NL, 0, BATCH>(a, bl, nlog, th, shm, s);
+  else if (nd == 1) fdm_launch_nd<T, DIM, NA, NL, 1, BATCH>(a, bl, nlog, th, shm, s);
+  else if constexpr (DIM == 3) fdm_launch_nd<T, DIM, NA, NL, 2, BATCH>(a, bl, nlog, th, shm, s);
   else return -4;
   return 0;
+}
+
+template <class T, int DIM, int NA, int NL>
+int fdm_launch_t(const LevelDev<T>& L, int nd, const T* r, T* out, int npx, int npy, int npz,
+                 int waves, const PatchLat& lat, hipStream_t s) {
+  FdmArgs<T> a;
+  a.L = L;
+  a.r = r;
+  a.out = out;
+  a.npx = npx;
+  a.npy = npy;
+  a.npz = npz;
+  a.lat = lat;
+  const int npatch = npx * npy * (DIM == 3 ? npz : 1);
+  return fdm_go<T, DIM, NA, NL, false>(nd, a, BatchList<FdmArgs<T>>{}, npatch, waves, s);
+}
+
+// One launch over the patch solves of many grids (same tile and normal): ntot
+// logical blocks, one per patch, grid g's patches in the range of bl.
+template <class T, int DIM, int NA, int NL>
+int fdm_batch_launch(int nd, const BatchList<FdmArgs<T>>& bl, int ntot, int waves, hipStream_t s) {
+  return fdm_go<T, DIM, NA, NL, true>(nd, FdmArgs<T>{}, bl, ntot, waves, s);
 }
 
 // ================================================================ multiplicative update
@@ -1113,17 +1247,45 @@ constexpr int combine_bpe() {
   return combine_epb<NP, DIM>() == 1 ? (ipow(NP, DIM) + COMBINE_CHUNK - 1) / COMBINE_CHUNK : 1;
 }
 
-template <class T, int DIM, int NP, int MAXC>
-__global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int NA, int NL,
-                                                      const T* __restrict__ buf, T* __restrict__ u,
-                                                      int npx, int npy, int npz, int nblk, bool assign) {
+template <class T>
+struct CombArgs {
+  LevelDev<T> L;
+  const T* buf = nullptr;  // the patch solve's weighted corrections
+  T* u = nullptr;
+  int nd = -1, NA = 0, NL = 0;
+  int npx = 1, npy = 1, npz = 1;
+  int nblk = 0;
+  int assign = 0;
+};
+
+// BATCH: the arguments come from the work list bl (ntot logical blocks in all)
+template <class T, int DIM, int NP, int MAXC, bool BATCH = false>
+__global__ void __launch_bounds__(256) combine_kernel(CombArgs<T> a0, BatchList<CombArgs<T>> bl, int ntot) {
   constexpr int NE = ipow(NP, DIM), EPB = combine_epb<NP, DIM>(), BPE = combine_bpe<NP, DIM>();
   constexpr int P = NP - 1;
   constexpr int CZ = DIM == 3 ? MAXC : 1;
   __shared__ int64_t cadr[EPB][3][NP][MAXC];
   __shared__ int ccnt[EPB][3][NP];
-  const int blk = xcd_block(nblk);
-  if (blk < 0 || inactive(L.active)) return;
+  __shared__ __align__(16) int sargs_raw[BATCH ? sizeof(CombArgs<T>) / sizeof(int) : 1];
+  CombArgs<T>* sargs = reinterpret_cast<CombArgs<T>*>(sargs_raw);
+  const CombArgs<T>* ap;
+  int blk;
+  if constexpr (BATCH) {
+    const int b = xcd_block(ntot);
+    if (b < 0) return;
+    blk = batch_pick(bl, b, sargs);
+    ap = sargs;
+  } else {
+    blk = xcd_block(a0.nblk);
+    if (blk < 0) return;
+    ap = &a0;
+  }
+  const LevelDev<T>& L = ap->L;
+  const T* __restrict__ buf = ap->buf;
+  T* __restrict__ u = ap->u;
+  const int nd = ap->nd, NA = ap->NA, NL = ap->NL, npx = ap->npx, npy = ap->npy;
+  const bool assign = ap->assign != 0;
+  if (inactive(L.active)) return;
   // BPE > 1: block blk takes nodes [q_lo, q_hi) of element blk / BPE
   const int e0 = BPE > 1 ? blk / BPE : blk * EPB;
   const int ne = BPE > 1 ? 1 : imin(EPB, L.n_elem - e0);
@@ -1197,18 +1359,50 @@ __global__ void __launch_bounds__(256) combine_kernel(LevelDev<T> L, int nd, int
   }
 }
 
+// Blocks of one grid's overlap summation.
+template <int DIM, int NP>
+int combine_blocks(int n_elem) {
+  constexpr int EPB = combine_epb<NP, DIM>(), BPE = combine_bpe<NP, DIM>();
+  return BPE > 1 ? n_elem * BPE : (n_elem + EPB - 1) / EPB;
+}
+// Candidate slots per node and direction: three covering element-centred
+// patches in one direction only when 2 N_O > N_P.
+inline int combine_maxc(int NP, int NO) { return 2 * NO > NP ? 3 : 2; }
+
 template <class T, int DIM, int NP>
 int combine_launch_t(const LevelDev<T>& L, int nd, int NA, int NL, const T* buf, T* u, int npx,
                      int npy, int npz, bool assign, hipStream_t s) {
-  constexpr int EPB = combine_epb<NP, DIM>(), BPE = combine_bpe<NP, DIM>();
-  const int nblk = BPE > 1 ? L.n_elem * BPE : (L.n_elem + EPB - 1) / EPB;
-  // three covering element-centred patches in one direction only when 2 N_O > N_P
-  if (2 * L.NO > NP)
-    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
-                       NL, buf, u, npx, npy, npz, nblk, assign);
+  CombArgs<T> a;
+  a.L = L;
+  a.buf = buf;
+  a.u = u;
+  a.nd = nd;
+  a.NA = NA;
+  a.NL = NL;
+  a.npx = npx;
+  a.npy = npy;
+  a.npz = npz;
+  a.nblk = combine_blocks<DIM, NP>(L.n_elem);
+  a.assign = assign ? 1 : 0;
+  if (combine_maxc(NP, L.NO) == 3)
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3, false>), dim3(xcd_grid(a.nblk)), dim3(256), 0, s, a,
+                       BatchList<CombArgs<T>>{}, a.nblk);
   else
-    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 2>), dim3(xcd_grid(nblk)), dim3(256), 0, s, L, nd, NA,
-                       NL, buf, u, npx, npy, npz, nblk, assign);
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 2, false>), dim3(xcd_grid(a.nblk)), dim3(256), 0, s, a,
+                       BatchList<CombArgs<T>>{}, a.nblk);
+  return 0;
+}
+
+// One launch over the overlap summations of many grids (same NP and candidate
+// slots maxc): ntot logical blocks, grid g's combine_blocks in the range of bl.
+template <class T, int DIM, int NP>
+int combine_batch_launch(int maxc, const BatchList<CombArgs<T>>& bl, int ntot, hipStream_t s) {
+  if (maxc == 3)
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 3, true>), dim3(xcd_grid(ntot)), dim3(256), 0, s, CombArgs<T>{},
+                       bl, ntot);
+  else
+    hipLaunchKernelGGL((combine_kernel<T, DIM, NP, 2, true>), dim3(xcd_grid(ntot)), dim3(256), 0, s, CombArgs<T>{},
+                       bl, ntot);
   return 0;
 }
 
@@ -1251,11 +1445,35 @@ __device__ __forceinline__ void xfer_pass(const T* __restrict__ sJ, const T* __r
   }
 }
 
-template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
-__global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, int n_elem,
-                                                       const T* __restrict__ in, T* __restrict__ out,
-                                                       const int* __restrict__ active) {
-  if (inactive(active)) return;
+template <class T>
+struct XferArgs {
+  const T* J = nullptr;
+  int n_elem = 0;
+  const T* in = nullptr;
+  T* out = nullptr;
+  const int* active = nullptr;
+};
+
+// BATCH: the arguments come from the work list bl (ntot logical blocks in all)
+template <class T, int DIM, int NPF, int NPC, bool RESTRICT, bool BATCH = false>
+__global__ void __launch_bounds__(512) transfer_kernel(XferArgs<T> a0, BatchList<XferArgs<T>> bl, int ntot) {
+  __shared__ __align__(16) int sargs_raw[BATCH ? sizeof(XferArgs<T>) / sizeof(int) : 1];
+  XferArgs<T>* sargs = reinterpret_cast<XferArgs<T>*>(sargs_raw);
+  const XferArgs<T>* ap;
+  int blk = blockIdx.x;
+  if constexpr (BATCH) {
+    const int b = xcd_block(ntot);
+    if (b < 0) return;
+    blk = batch_pick(bl, b, sargs);
+    ap = sargs;
+  } else {
+    ap = &a0;
+  }
+  const T* __restrict__ J = ap->J;
+  const int n_elem = ap->n_elem;
+  const T* __restrict__ in = ap->in;
+  T* __restrict__ out = ap->out;
+  if (inactive(ap->active)) return;
   constexpr int NEF = ipow(NPF, DIM), EPB = xfer_epb<NPF, DIM>();
   constexpr int NIN = RESTRICT ? NPF : NPC, NOUT = RESTRICT ? NPC : NPF;
   constexpr int NEI = ipow(NIN, DIM), NEO = ipow(NOUT, DIM);
@@ -1263,7 +1481,7 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufB = bufA + EPB * NEF;
   __shared__ T sJ[NPF * NPC];
-  const int e0 = blockIdx.x * EPB;
+  const int e0 = blk * EPB;
   const int ne = imin(EPB, n_elem - e0);
   staged_copy<T, XFER_THREADS, NPF * NPC>([&](int q) { return J[q]; }, [&](int q, T v) { sJ[q] = v; });
   staged_copy<T, XFER_THREADS, EPB * NEI>([&](int q) { return in[(int64_t)e0 * NEI + q]; },
@@ -1295,16 +1513,43 @@ __global__ void __launch_bounds__(512) transfer_kernel(const T* __restrict__ J, 
                                             ne * NEO);
 }
 
-template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
-int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* active, hipStream_t s) {
+// Blocks of one grid's transfer.
+template <int DIM, int NPF>
+int xfer_blocks(int n_elem) {
   constexpr int EPB = xfer_epb<NPF, DIM>();
-  const int nb = (n_elem + EPB - 1) / EPB;
+  return (n_elem + EPB - 1) / EPB;
+}
+
+template <class T, int DIM, int NPF, int NPC, bool RESTRICT, bool BATCH>
+void transfer_go(const XferArgs<T>& a, const BatchList<XferArgs<T>>& bl, int nblk, hipStream_t s) {
+  constexpr int EPB = xfer_epb<NPF, DIM>();
   const size_t shm = 2 * (size_t)EPB * ipow(NPF, DIM) * sizeof(T);
   if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)transfer_kernel<T, DIM, NPF, NPC, RESTRICT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT>), dim3(nb), dim3(XFER_THREADS), shm, s, J,
-                     n_elem, in, out, active);
+    (void)hipFuncSetAttribute((const void*)transfer_kernel<T, DIM, NPF, NPC, RESTRICT, BATCH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const int grid = BATCH ? xcd_grid(nblk) : nblk;
+  hipLaunchKernelGGL((transfer_kernel<T, DIM, NPF, NPC, RESTRICT, BATCH>), dim3(grid), dim3(XFER_THREADS), shm, s,
+                     a, bl, nblk);
+}
+
+template <class T, int DIM, int NPF, int NPC, bool RESTRICT>
+int transfer_launch_t(const T* J, int n_elem, const T* in, T* out, const int* active, hipStream_t s) {
+  XferArgs<T> a;
+  a.J = J;
+  a.n_elem = n_elem;
+  a.in = in;
+  a.out = out;
+  a.active = active;
+  transfer_go<T, DIM, NPF, NPC, RESTRICT, false>(a, BatchList<XferArgs<T>>{}, xfer_blocks<DIM, NPF>(n_elem), s);
+  return 0;
+}
+
+// One launch over the transfers of many grids (same order pair and direction):
+// ntot logical blocks, grid g's xfer_blocks in the range of bl.
+template <class T, int DIM, int NPF, int NPC>
+int transfer_batch_launch(bool restrict_, const BatchList<XferArgs<T>>& bl, int ntot, hipStream_t s) {
+  if (restrict_) transfer_go<T, DIM, NPF, NPC, true, true>(XferArgs<T>{}, bl, ntot, s);
+  else transfer_go<T, DIM, NPF, NPC, false, true>(XferArgs<T>{}, bl, ntot, s);
   return 0;
 }
 
@@ -1323,6 +1568,19 @@ struct Kern {
   // u += the unweighted corrections of one patch-solve launch (disjoint patches)
   static int mult_update(const LevelDev<T>& L, int nd, int NA, int NL, const PatchLat& lat, int npx, int npy,
                          int npz, const T* buf, T* u, hipStream_t s);
+  // Batched launches (work lists over many grids, see BatchList): the same
+  // kernels as above with per-grid arguments.  Block counts per grid:
+  // apply_blocks, one per patch, combine_blocks, xfer_blocks.  -4 where the
+  // template is not built.
+  static int apply_blocks_of(int NP, int n_elem);
+  static int combine_blocks_of(int NP, int n_elem);
+  static int xfer_blocks_of(int NPF, int n_elem);
+  static bool mode3_ok(const LevelDev<T>& L);
+  static int apply_batch(int NP, int mode, const BatchList<ApplyArgs<T>>& bl, int ntot, hipStream_t s);
+  static int fdm_batch(int nd, int NA, int NL, const BatchList<FdmArgs<T>>& bl, int ntot, int waves, hipStream_t s);
+  static int combine_batch(int NP, int maxc, const BatchList<CombArgs<T>>& bl, int ntot, hipStream_t s);
+  static int transfer_batch(int NPF, int NPC, bool restrict_, const BatchList<XferArgs<T>>& bl, int ntot,
+                            hipStream_t s);
   static bool fdm_supported(int NA, int NL);
   // the tile's solve runs in LDS (not the large-tile stages through global memory)
   static bool fdm_in_lds(int NA, int NL);

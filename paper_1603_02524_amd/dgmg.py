@@ -89,6 +89,7 @@ SIGNATURES = [
     ("dgmg_apply_mlp", c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, POINTER(c_double)]),
     ("dgmg_batch_setup", c_int, [c_int, POINTER(DgmgGrid), POINTER(DgmgOpts), POINTER(c_void_p)]),
     ("dgmg_batch_workspace_bytes", c_int, [c_void_p, POINTER(c_size_t)]),
+    ("dgmg_batch_plan_info", c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     ("dgmg_batch_bind_workspace", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
     ("dgmg_batch_offsets", c_int, [c_void_p, POINTER(c_int64)]),
     ("dgmg_batch_handle", c_int, [c_void_p, c_int, POINTER(c_void_p)]),
@@ -507,6 +508,12 @@ class BatchSolver:
         if rc not in allow:
             raise DgmgError(rc, self.lib.dgmg_batch_last_error(self.b).decode())
         return rc
+
+    def plan_info(self):
+        """(planned, batched kernel launches per iteration, per-grid operations per iteration)."""
+        p, k, g = c_int(), c_int(), c_int()
+        self._check(self.lib.dgmg_batch_plan_info(self.b, ctypes.byref(p), ctypes.byref(k), ctypes.byref(g)))
+        return bool(p.value), k.value, g.value
 
     @property
     def n_dof(self):

@@ -160,3 +160,57 @@ def test_face_features_match_oracle(name):
     ref = learned.face_features(w.grid, w.method)
     assert X.shape == ref.shape
     assert np.allclose(X, ref, rtol=0, atol=2e-7)
+
+
+def _batch(lib, probs):
+    k = len(probs)
+    grids = (D.DgmgGrid * k)()
+    opts = (D.DgmgOpts * k)()
+    keep = []
+    for i, (g, m) in enumerate(probs):
+        gg, oo, kk = D.make_structs(g, m)
+        grids[i], opts[i] = gg, oo
+        keep.append(kk)
+    b = ctypes.c_void_p()
+    assert lib.dgmg_batch_setup(k, grids, opts, ctypes.byref(b)) == 0
+    return b, keep
+
+
+def _plan(lib, b):
+    p, kk, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.dgmg_batch_plan_info(b, ctypes.byref(p), ctypes.byref(kk), ctypes.byref(g)) == 0
+    return p.value, kk.value, g.value
+
+
+def test_batch_plan_host_side():
+    """The batched execution plan (host only, before any device memory): grids of
+    one precision and smoothing schedule merge their kernel steps into shared
+    launches, so the launch count per iteration grows with the number of distinct
+    (order, tile) shapes, not with the number of grids; a multiplicative grid in
+    the batch turns the plan off (each grid then issues its own chain)."""
+    lib = D.load_library()
+    rng = np.random.default_rng(2)
+
+    def grid(n):
+        return synth.Grid(3, tuple(rng.uniform(0.5, 1.5, n) for _ in range(3)), (False,) * 3)
+
+    one = [(grid(2), synth.Method(P=8, smoother="FA", precision="mixed"))]
+    many = one + [(grid(int(rng.integers(1, 4))), synth.Method(P=8, smoother="FA", precision="mixed"))
+                  for _ in range(15)]
+    b1, k1 = _batch(lib, one)
+    b16, k16 = _batch(lib, many)
+    try:
+        p1, n1, g1 = _plan(lib, b1)
+        p16, n16, g16 = _plan(lib, b16)
+        assert p1 == 1 and p16 == 1
+        assert n16 == n1                    # same orders and tiles: the same launches, 16 grids each
+        assert g16 == 16 * g1               # per-grid operations scale with the grids
+    finally:
+        lib.dgmg_batch_destroy(b1)
+        lib.dgmg_batch_destroy(b16)
+    mixed_kinds = [(grid(2), synth.Method(P=4, smoother="FA")), (grid(2), synth.Method(P=4, smoother="FM"))]
+    b, k = _batch(lib, mixed_kinds)
+    try:
+        assert _plan(lib, b)[0] == 0
+    finally:
+        lib.dgmg_batch_destroy(b)

@@ -4,7 +4,9 @@
   work of the program in between;
 * autotuning changes only the block shapes: results stay bitwise identical;
 * a batch of grids of uneven order and size reproduces the single-grid solver
-  bitwise and the oracle to 1e-10;
+  bitwise and the oracle to 1e-10, with its phases run as work-list plans
+  (launches shared by the grids) and, when the grids cannot share launches,
+  per grid;
 * the 64-grid batched workload (elements 4^3..16^3, P in {4,6,8,12,16}, aspect
   ratios up to 8, FP32 multigrid in FP64 MGCG) converges every grid to the
   1e-10 true residual."""
@@ -169,6 +171,9 @@ def test_batched_64_grid_workload():
     probs = [(w.grid, w.method) for w in ws]
     print(f"[c4] total dof {sum(w.n_dof for w in ws)}", flush=True)
     B = D.BatchSolver(probs, max_iter=60)
+    planned, kernels, grid_ops = B.plan_info()
+    print(f"[c4] plan: {kernels} batched launches and {grid_ops} per-grid operations per iteration", flush=True)
+    assert planned
     rhs = np.concatenate([synth.rhs_uniform(w.seed, w.n_dof) for w in ws])
     f = _dev(rhs)
     x = _dev(np.zeros(B.n_dof))
@@ -183,3 +188,30 @@ def test_batched_64_grid_workload():
         assert res <= bound, (i, res / np.linalg.norm(fh[sl]), bound / np.linalg.norm(fh[sl]))
         assert stats[i]["r_true"] <= 1e-10 * stats[i]["r0"], i
     B.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_unplanned_batch_matches_single(graphs):
+    """A batch whose grids cannot share launches (here a multiplicative grid next
+    to an additive one) issues each grid's chain on its own and still equals the
+    single-grid solves bit for bit."""
+    probs = [(rand_grid(3, (2, 2, 2), seed=44), synth.Method(P=4, smoother="FA")),
+             (rand_grid(3, (3, 2, 2), seed=45), synth.Method(P=4, smoother="FM", order="colour"))]
+    B = D.BatchSolver(probs)
+    try:
+        assert B.plan_info()[0] is False
+        B.use_graphs(graphs)
+        f_all = np.random.default_rng(6).uniform(-1, 1, B.n_dof)
+        x_all = _dev(np.zeros(B.n_dof))
+        stats = B.solve(_dev(f_all), x_all)
+        xb = x_all.cpu().numpy()
+        for i, (g, m) in enumerate(probs):
+            sl = slice(B.offsets[i], B.offsets[i + 1])
+            S = D.Solver(g, m)
+            xs = _dev(np.zeros(sl.stop - sl.start))
+            st = S.solve(_dev(f_all[sl]), xs)
+            assert stats[i]["converged"] and st["iterations"] == stats[i]["iterations"], i
+            assert np.array_equal(xs.cpu().numpy(), xb[sl]), i
+            S.close()
+    finally:
+        B.close()
