@@ -109,6 +109,13 @@ def load_library(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise OSError(f"{path} not found: build it with `python -m paper_1603_02524_amd.build_lib`")
+        # torch first: the HIP runtime it loads then serves the library too (loaded
+        # the other way round, the two can end up with separate runtimes, and the
+        # library's finds no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # host-only use (setup, tables) needs no torch
+            pass
         lib = ctypes.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(lib, name)

@@ -183,7 +183,9 @@ def test_fullsize_fp64_solve_matches_oracle_mgcg():
 
 def test_fullsize_learned_weights_no_worse(big):
     """Learned face weights (shipped network, probe fallback) on the full workload:
-    the solve still reaches the true residual and takes no more iterations."""
+    the solve still reaches the true residual and takes no more iterations; on the
+    8^3 P = 32 workload with aspect ratios up to 32 it takes strictly fewer
+    (7 -> 6 with the shipped network)."""
     import os
     from paper_1603_02524_amd import learn
     name, w, S, H = big
@@ -208,3 +210,5 @@ def test_fullsize_learned_weights_no_worse(big):
           f"iterations, rho {st['rho']:.4f} vs {fixed['rho']:.4f}, true residual {res / np.linalg.norm(fl):.2e}")
     assert st["converged"] and res <= bound
     assert st["iterations"] <= fixed["iterations"]
+    if name.startswith("c5"):
+        assert kept and st["iterations"] < fixed["iterations"]
