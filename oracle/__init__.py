@@ -21,6 +21,9 @@ schwarz    element- and face-centred subdomains, weights, dense and
            fast-diagonalisation patch solves, additive Schwarz sweeps (Sec. 3.1).
 multigrid  level series, transfers, exact coarse solve, V-cycle (Alg. 1) and
            inexact MG-preconditioned CG (Alg. 2).
+se         the continuous spectral-element counterpart of Sec. 4.3: direct
+           stiffness summation, transfers, element-centred weighted additive
+           Schwarz on continuous subdomains (the V-cycle and MGCG are shared).
 metrics    convergence and cost measures of Sec. 4.1.
 mlp        FP64 reference of the small overlap-weight network (not in the paper).
 
