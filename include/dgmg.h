@@ -29,6 +29,21 @@
  *   otherwise.  A handle must not be used from two host threads at once.
  * dtype: DGMG_F64 (double) or DGMG_F32 (float) selects the element type of
  *   the vector arguments of level operations; tables exist in both precisions.
+ * Continuous counterpart (opts.disc = DGMG_DISC_SE; Sec. 4.3 compares it with
+ *   the DG method): C0 spectral elements of order P on the same grid, system
+ *   matrix by direct stiffness summation of the GLL element Laplacians, the
+ *   same V-cycle and MGCG, and the element-centred weighted additive smoother
+ *   (DGMG_SMOOTHER_EA only) on continuous subdomains: element m's nodes plus
+ *   N_O node layers of each neighbour beyond the shared boundary node, N_O =
+ *   (the DG overlap value) - 1, so that the subdomain covers the same region
+ *   and excludes the same node layer as the DG one (the DG subdomain counts
+ *   the neighbour node coinciding with the element's own as a layer); overlap
+ *   width eta_{N_O+1} + 1; weights of eq. (weight function:ec).  Vectors of
+ *   such a handle are LATTICE vectors: per direction the node positions
+ *   g = m P + i (neighbouring elements share g = m P); a Dirichlet direction
+ *   stores g = 1 .. N P - 1 at index g - 1 (nl = N P - 1 entries), a periodic
+ *   one g mod N P (nl = N P); entry s1 + nl1 (s2 + nl2 s3).  3D needs P <= 16;
+ *   flux, beta and mu_star are ignored; batches take DG grids only.
  * Errors: 0 on success; > 0 non-fatal status (DGMG_NOT_CONVERGED,
  *   DGMG_FELLBACK); < 0 error
  *   (DGMG_EINVAL bad argument, DGMG_EHIP runtime failure, DGMG_ENOMEM
@@ -84,6 +99,9 @@ extern "C" {
 #define DGMG_VCYCLE_CLASSICAL 0 /* (N_S1, N_S2) on every level */
 #define DGMG_VCYCLE_VARIABLE 1  /* counts doubled on each coarser level */
 
+#define DGMG_DISC_DG 0 /* nodal DG (eq. (discrete problem)) */
+#define DGMG_DISC_SE 1 /* the continuous spectral-element counterpart (Sec. 4.3), see below */
+
 #define DGMG_PREC_FP64 0  /* everything in double precision */
 #define DGMG_PREC_MIXED 1 /* V-cycle in float (coarse solve in double) inside FP64 PCG */
 
@@ -112,6 +130,7 @@ typedef struct {
   int precision;     /* DGMG_PREC_* */
   int max_iter;      /* i_max of Alg. 2 */
   int order;         /* DGMG_ORDER_* (multiplicative smoothers; ignored otherwise) */
+  int disc;          /* DGMG_DISC_* (default DGMG_DISC_DG) */
 } dgmg_opts;
 
 /* Statistics of one dgmg_solve call (host struct, filled on return). */
@@ -162,7 +181,8 @@ int dgmg_level_info(const dgmg_handle* h, int level, int* P, int* n_o, int64_t* 
 
 /* Host copy of the 1D node coordinates of level `level` in direction d
  * (n_elem[d] * (P_l + 1) doubles, element by element; element map of
- * Sec. 2.2 with the grid starting at 0). */
+ * Sec. 2.2 with the grid starting at 0).  Continuous handles: the nl stored
+ * lattice nodes of the direction. */
 int dgmg_node_coords(const dgmg_handle* h, int level, int d, double* x_host);
 
 /* y = A_l x (eq. (discrete problem); sum factorised).  x, y: device vectors
@@ -234,7 +254,7 @@ int dgmg_vcycle(dgmg_handle* h, const void* r, void* z, int dtype);
 int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_stats* st);
 
 /* g = M f: the GLL load vector of Sec. 2.4 from nodal values f (FP64 device
- * vectors of the top level). */
+ * vectors of the top level; continuous handles: the assembled lumped mass). */
 int dgmg_mass(dgmg_handle* h, const double* f_nodal, double* g);
 
 /* Per-kernel timing with HIP events on the handle's stream.  enable != 0

@@ -192,6 +192,23 @@ def assemble(grid, P: int) -> sp.csr_matrix:
     return A.tocsr()
 
 
+def assemble_kron(grid, P: int) -> sp.csr_matrix:
+    """The same matrix as ``assemble`` in the Kronecker form of the assembled 1D
+    matrices, sum_d (x)_{d' != d} M_{d'} (x) L_d (the elements are tensor cells;
+    equality with the element loop is pinned by the tests).  Sparse, so it also
+    serves grids whose dense element matrices would be too large."""
+    dim = grid.dim
+    ops = [assemble_1d(P, grid.dx[d], grid.periodic[d]) for d in range(dim)]
+    A = None
+    for d in range(dim):
+        t = sp.identity(1, format="csr")
+        for dd in reversed(range(dim)):
+            B = sp.csr_matrix(ops[dd][1]) if dd == d else sp.diags(ops[dd][0])
+            t = sp.kron(t, B, format="csr")
+        A = t if A is None else A + t
+    return A.tocsr()
+
+
 def apply(grid, P: int, u: np.ndarray) -> np.ndarray:
     """A u matrix-free: per element gather, local operator, scatter-add."""
     dim = grid.dim
@@ -406,7 +423,7 @@ class SEHierarchy:
         self.orders = level_orders(method.P)
         self.levels: List[SELevel] = []
         for l, Pl in enumerate(self.orders):
-            A = assemble(grid, Pl) if (assemble_all or l == 0 or patch_mode == "dense") else None
+            A = assemble_kron(grid, Pl) if (assemble_all or l == 0 or patch_mode == "dense") else None
             sm = None
             if l > 0:
                 sm = SESmoother(grid, Pl, se_overlap(Pl, method.overlap), method.weighting, A, patch_mode)

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dgmg.h"
@@ -241,6 +242,8 @@ __global__ void __launch_bounds__(VEC_THREADS) k_mass(LevelDev<double> L, const 
 // element-major P = 1 vector: out = (S_d^T or S_d) applied along d.
 struct CoarseDev {
   int dim;
+  int se;     // 1: continuous lattice vector (nl[d] nodes per direction)
+  int nl[3];
   int N[3];
   const double* S[3];    // G_d x G_d row-major
   const double* lam[3];  // G_d
@@ -288,6 +291,62 @@ __global__ void __launch_bounds__(VEC_THREADS) k_coarse_pass(CoarseDev C, int d,
     s = den != 0.0 ? s / den : 0.0;
   }
   out[q] = s;
+}
+
+// The same pass on a continuous lattice vector (nl[d] nodes per direction,
+// direction 1 fastest).
+template <bool FWD, bool SCALE>
+__global__ void __launch_bounds__(VEC_THREADS) k_coarse_pass_lat(CoarseDev C, int d, const double* __restrict__ in,
+                                                                 double* __restrict__ out, int64_t n,
+                                                                 const int* act) {
+  if (inactive(act)) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int dim = C.dim;
+  int s[3] = {0, 0, 0};
+  int64_t rest = q;
+  for (int e = 0; e < dim; ++e) {
+    s[e] = (int)(rest % C.nl[e]);
+    rest /= C.nl[e];
+  }
+  const int G = C.nl[d], I = s[d];
+  const int64_t st = d == 0 ? 1 : (d == 1 ? (int64_t)C.nl[0] : (int64_t)C.nl[0] * C.nl[1]);
+  const int64_t base = q - (int64_t)I * st;
+  const double* S = C.S[d];
+  double acc = 0.0;
+  for (int K = 0; K < G; ++K) acc += (FWD ? S[(int64_t)K * G + I] : S[(int64_t)I * G + K]) * in[base + K * st];
+  if (SCALE) {
+    double den = 0.0;
+    for (int dd = 0; dd < dim; ++dd) den += C.lam[dd][s[dd]];
+    acc = den != 0.0 ? acc / den : 0.0;
+  }
+  out[q] = acc;
+}
+
+// g = M f on a continuous lattice (assembled GLL-lumped mass: per direction the
+// sum over the elements sharing the node of (dx/2) rho_i).
+__global__ void __launch_bounds__(VEC_THREADS) k_mass_se(LevelDev<double> L, const double* __restrict__ f,
+                                                         double* __restrict__ g) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.n_dof) return;
+  const int P = L.P;
+  int64_t rest = q;
+  double w = 1.0;
+  for (int d = 0; d < L.dim; ++d) {
+    const DirDev<double>& dd = L.dir[d];
+    const int s = (int)(rest % dd.nl);
+    rest /= dd.nl;
+    const int gl = dd.periodic ? s : s + 1;
+    const int m = gl / P, i = gl - m * P;
+    double md;
+    if (i != 0) md = dd.ecoef[m * ECOEF_N + E_HALF_DX] * L.rho[i];
+    else {
+      const int ml = m == 0 ? dd.N - 1 : m - 1;
+      md = dd.ecoef[ml * ECOEF_N + E_HALF_DX] * L.rho[P] + dd.ecoef[m * ECOEF_N + E_HALF_DX] * L.rho[0];
+    }
+    w *= md;
+  }
+  g[q] = w * f[q];
 }
 
 inline unsigned vec_blocks(int64_t n) {
@@ -523,6 +582,20 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
     int64_t nst = 1;
     for (int e = 0; e < dir; ++e) nst *= NP;
     std::vector<int> t((size_t)npatch * len);
+    if (h.se) {  // lattice vectors: patch q's tile starts at lattice position q P - N_O
+      int64_t lst = 1;
+      for (int e = 0; e < dir; ++e) lst *= h.dir[e].nl;
+      const int NT = s.N * h.P;
+      for (int q = 0; q < npatch; ++q)
+        for (int o = 0; o < len; ++o) {
+          const int g = q * h.P - h.NO + o;
+          int st = -1;
+          if (s.periodic) st = ((g % NT) + NT) % NT;
+          else if (g >= 1 && g <= NT - 1) st = g - 1;
+          t[(size_t)q * len + o] = st < 0 ? -1 : (int)(st * lst);
+        }
+      return t;
+    }
     for (int q = 0; q < npatch; ++q)
       for (int o = 0; o < len; ++o) {
         int g = (fc ? (q - 1) * NP + 1 : q * NP - h.NO) + o;
@@ -534,6 +607,7 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
     return t;
   };
   d.dim = h.dim;
+  d.se = h.se ? 1 : 0;
   d.P = h.P;
   d.NP = h.NP;
   d.NO = h.NO;
@@ -551,6 +625,7 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
     const Dir1D& s = h.dir[k];
     dd.N = s.N;
     dd.periodic = s.periodic;
+    dd.nl = s.nl;
     dd.n_ec = s.n_ec;
     dd.n_fc = s.n_fc;
     dd.nf = s.nf;
@@ -561,12 +636,14 @@ void carve_level(Carver& cv, const LevelHost& h, LevelDev<T>& d, Upload* up) {
       dd.ST_ec = put(transp(s.S_ec, s.n_ec));
       dd.lam_ec = put(s.lam_ec);
       dd.w_ec = put(s.w_ec);
-      dd.S_fc = put(s.S_fc);
-      dd.ST_fc = put(transp(s.S_fc, s.n_fc));
-      dd.lam_fc = put(s.lam_fc);
-      dd.w_fc = put(s.w_fc);
+      if (!h.se) {  // continuous levels have element-centred subdomains only
+        dd.S_fc = put(s.S_fc);
+        dd.ST_fc = put(transp(s.S_fc, s.n_fc));
+        dd.lam_fc = put(s.lam_fc);
+        dd.w_fc = put(s.w_fc);
+      }
       dd.goff_ec = put_int(offsets(k, s.N, s.n_ec, false));
-      dd.goff_fc = put_int(offsets(k, s.nf, s.n_fc, true));
+      if (!h.se) dd.goff_fc = put_int(offsets(k, s.nf, s.n_fc, true));
     }
   }
 }
@@ -594,8 +671,10 @@ void layout(dgmg_handle* h, char* base, Upload* up) {
   }
   const LevelHost& l0 = h->lv[0];
   h->cdev.dim = l0.dim;
+  h->cdev.se = l0.se ? 1 : 0;
   for (int d = 0; d < 3; ++d) {
     h->cdev.N[d] = d < l0.dim ? l0.dir[d].N : 1;
+    h->cdev.nl[d] = d < l0.dim ? l0.dir[d].nl : 1;
     if (d >= l0.dim) continue;
     const Dir1D& s = l0.dir[d];
     void* pS = cv.take(s.S_glob.size() * sizeof(double));
@@ -624,6 +703,12 @@ void layout(dgmg_handle* h, char* base, Upload* up) {
     }
   }
   pmax = std::max(pmax, (size_t)l0.n_dof);
+  for (int l = 0; l < nl; ++l)  // continuous levels: element-major copies of the apply and restriction
+    if (h->lv[l].se) {
+      size_t ne = (size_t)h->lv[l].n_elem;
+      for (int d = 0; d < h->lv[l].dim; ++d) ne *= h->lv[l].NP;
+      pmax = std::max(pmax, ne);
+    }
   for (int l = 1; l < nl; ++l)  // scratch of the transfers and the apply of large 3D elements
     if (h->lv[l].dim == 3 && h->lv[l].NP == BIG_NP) {
       pmax = std::max(pmax, (size_t)transfer_big_scratch((int)h->lv[l].n_elem, h->lv[l].NP, h->lv[l].NPc));
@@ -668,6 +753,21 @@ template <class T>
 int k_apply(dgmg_handle* h, int l, int mode, const T* x, const T* f, T* y, double* part, int* nb) {
   const LevelDev<T>& L = LD<T>(h, l);
   T* scratch = (T*)h->patch;  // idle outside the patch solves of a sweep
+  if (L.se) {  // element copies into the patch buffer, then the node sums
+    const int m = mode == 2 ? 0 : mode;
+    int rc = L.dim == 3 ? Kern<T, 3>::se_apply(L, m, x, f, y, scratch, h->stream)
+                        : Kern<T, 2>::se_apply(L, m, x, f, y, scratch, h->stream);
+    if (rc) return fail(h, DGMG_EUNSUPPORTED, "no continuous operator kernel for this order");
+    if (mode == 2) {  // partial sums of x.y for the PCG
+      if constexpr (std::is_same<T, double>::value) {
+        hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, y, L.n_dof, part, h->active);
+        *nb = RED_BLOCKS;
+      } else {
+        return fail(h, DGMG_EINVAL, "mode 2 is FP64 only");
+      }
+    }
+    return check_hip(h, "apply");
+  }
   int rc = L.dim == 3 ? Kern<T, 3>::apply(L, mode, x, f, y, scratch, part, nb, h->stream)
                       : Kern<T, 2>::apply(L, mode, x, f, y, scratch, part, nb, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no operator kernel for this order");
@@ -745,8 +845,12 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero =
   if (rc) return rc;
   T* pb = (T*)h->patch;
   // u == 0 on entry: the overlap sum is assigned (no fill of u beforehand, no read of it)
-  rc = L.dim == 3 ? Kern<T, 3>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream)
-                  : Kern<T, 2>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream);
+  if (L.se)
+    rc = L.dim == 3 ? Kern<T, 3>::se_combine(L, NA, pb, u, u_zero, h->stream)
+                    : Kern<T, 2>::se_combine(L, NA, pb, u, u_zero, h->stream);
+  else
+    rc = L.dim == 3 ? Kern<T, 3>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream)
+                    : Kern<T, 2>::combine(L, nd, NA, NL, pb, u, np[0], np[1], np[2], u_zero, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no combine kernel for this order");
   return check_hip(h, "combine");
 }
@@ -831,6 +935,13 @@ template <class T>
 int k_transfer(dgmg_handle* h, int l, bool restr, const T* in, T* out) {
   const LevelDev<T>& L = LD<T>(h, l);
   T* tmp = (T*)h->patch;
+  if (L.se) {
+    const LevelDev<T>& Lc = LD<T>(h, l - 1);
+    int rc = L.dim == 3 ? Kern<T, 3>::se_transfer(L, Lc, restr, in, out, tmp, h->stream)
+                        : Kern<T, 2>::se_transfer(L, Lc, restr, in, out, tmp, h->stream);
+    if (rc) return fail(h, DGMG_EUNSUPPORTED, "no continuous transfer kernel for this order pair");
+    return check_hip(h, "transfer");
+  }
   int rc = L.dim == 3 ? Kern<T, 3>::transfer(L, restr, in, out, tmp, h->stream)
                       : Kern<T, 2>::transfer(L, restr, in, out, tmp, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no transfer kernel for this order pair");
@@ -845,7 +956,7 @@ int k_residual_restrict(dgmg_handle* h, int l, const T* u, const T* f, T* r_scra
   const LevelDev<T>& L = LD<T>(h, l);
   T* scratch = (T*)h->patch;
   int rc = -4;
-  if (h->fuse_restrict)
+  if (h->fuse_restrict && !L.se)
     rc = L.dim == 3 ? Kern<T, 3>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream)
                     : Kern<T, 2>::apply(L, 3, u, f, fc, scratch, nullptr, nullptr, h->stream);
   if (rc == 0) return check_hip(h, "residual restriction");
@@ -883,7 +994,12 @@ int coarse_fdm(dgmg_handle* h, const double* f0, double* u0) {
   int k = 0;
   for (int d = 0; d < dim; ++d) {
     double* out = bufs[k];
-    if (d == dim - 1)
+    if (h->cdev.se) {
+      if (d == dim - 1)
+        hipLaunchKernelGGL((k_coarse_pass_lat<true, true>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
+      else
+        hipLaunchKernelGGL((k_coarse_pass_lat<true, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
+    } else if (d == dim - 1)
       hipLaunchKernelGGL((k_coarse_pass<true, true>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
     else
       hipLaunchKernelGGL((k_coarse_pass<true, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
@@ -892,7 +1008,10 @@ int coarse_fdm(dgmg_handle* h, const double* f0, double* u0) {
   }
   for (int d = dim - 1; d >= 0; --d) {
     double* out = d == 0 ? u0 : bufs[k];
-    hipLaunchKernelGGL((k_coarse_pass<false, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
+    if (h->cdev.se)
+      hipLaunchKernelGGL((k_coarse_pass_lat<false, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
+    else
+      hipLaunchKernelGGL((k_coarse_pass<false, false>), dim3(nb), dim3(VEC_THREADS), 0, h->stream, h->cdev, d, in, out, n, h->active);
     in = out;
     k ^= 1;
   }
@@ -1189,6 +1308,13 @@ int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   if (o->precision != DGMG_PREC_FP64 && o->precision != DGMG_PREC_MIXED) return fail(nullptr, DGMG_EINVAL, "bad precision");
   if (o->ns_pre < 0 || o->ns_post < 0 || o->max_iter < 0) return fail(nullptr, DGMG_EINVAL, "negative count");
   if (o->overlap < -2) return fail(nullptr, DGMG_EINVAL, "bad overlap");
+  if (o->disc != DGMG_DISC_DG && o->disc != DGMG_DISC_SE) return fail(nullptr, DGMG_EINVAL, "bad discretisation");
+  if (o->disc == DGMG_DISC_SE) {
+    if (o->smoother != DGMG_SMOOTHER_EA)
+      return fail(nullptr, DGMG_EUNSUPPORTED, "the continuous counterpart uses the element-centred additive smoother");
+    if (g->dim == 3 && o->P > 16)
+      return fail(nullptr, DGMG_EUNSUPPORTED, "continuous 3D levels need P <= 16 (element tiles in LDS)");
+  }
   sp = SetupParams();
   sp.dim = g->dim;
   for (int d = 0; d < g->dim; ++d) {
@@ -1211,6 +1337,7 @@ int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   sp.mu_star = o->mu_star;
   sp.smoother = o->smoother;
   sp.overlap = o->overlap;
+  sp.disc = o->disc;
   // multiplicative Schwarz adds its corrections unweighted: unit weight tables
   sp.weighting = mult ? DGMG_WEIGHT_NONE : o->weighting;
   return DGMG_OK;
@@ -1398,6 +1525,19 @@ int dgmg_node_coords(const dgmg_handle* h, int level, int d, double* x) {
   const LevelHost& lv = h->lv[level];
   std::vector<double> eta, rho;
   gll_points(lv.P, eta, rho);
+  if (lv.se) {  // stored lattice nodes of the direction
+    const Dir1D& dd = lv.dir[d];
+    const int shift = dd.periodic ? 0 : 1;
+    double left = 0.0;
+    for (int m = 0; m < dd.N; ++m) {
+      for (int i = 0; i < lv.P; ++i) {
+        const int s = m * lv.P + i - shift;
+        if (s >= 0 && s < dd.nl) x[s] = left + 0.5 * (1.0 + eta[i]) * dd.dx[m];
+      }
+      left += dd.dx[m];
+    }
+    return DGMG_OK;
+  }
   double left = 0.0;
   for (int m = 0; m < lv.dir[d].N; ++m) {
     const double hh = lv.dir[d].dx[m];
@@ -1438,6 +1578,7 @@ int dgmg_sweep(dgmg_handle* h, int level, void* u, const void* f, int normal, in
   if (rc || (rc = check_level(h, level, 1))) return rc;
   const LevelHost& lv = h->lv[level];
   if (!u || !f || normal < -1 || normal >= lv.dim) return fail(h, DGMG_EINVAL, "bad arguments");
+  if (lv.se && normal != -1) return fail(h, DGMG_EINVAL, "continuous levels have element-centred subdomains only");
   int np[3], NA, NL;
   sweep_shape(lv, normal, np, NA, NL);
   const bool ok = lv.dim == 3 ? Kern<double, 3>::fdm_supported(NA, NL) : Kern<double, 2>::fdm_supported(NA, NL);
@@ -1487,7 +1628,8 @@ int dgmg_mass(dgmg_handle* h, const double* f, double* g) {
   int rc = need_bound(h);
   if (rc) return rc;
   const LevelDev<double>& L = h->Ld.back();
-  hipLaunchKernelGGL(k_mass, dim3((unsigned)((L.n_dof + 255) / 256)), dim3(256), 0, h->stream, L, f, g);
+  if (L.se) hipLaunchKernelGGL(k_mass_se, dim3((unsigned)((L.n_dof + 255) / 256)), dim3(256), 0, h->stream, L, f, g);
+  else hipLaunchKernelGGL(k_mass, dim3((unsigned)((L.n_dof + 255) / 256)), dim3(256), 0, h->stream, L, f, g);
   return check_hip(h, "mass");
 }
 
@@ -2228,6 +2370,11 @@ int dgmg_batch_setup(int count, const dgmg_grid* grids, const dgmg_opts* opts, d
       return rc;
     }
     b->h.push_back(h);
+    if (h->sp.disc != DGMG_DISC_DG) {
+      for (auto* x : b->h) dgmg_destroy(x);
+      delete b;
+      return fail(nullptr, DGMG_EUNSUPPORTED, "grid " + std::to_string(i) + ": batches take DG grids only");
+    }
     cv.off = (cv.off + 255) & ~size_t(255);  // member workspaces: 256-aligned, disjoint
     b->sub_off.push_back(cv.off);
     cv.off += h->ws_need;

@@ -4,6 +4,7 @@
 
 #include "kernels.hpp"
 #include "kernels_big.hpp"
+#include "kernels_se.hpp"
 
 namespace dgmg {
 
@@ -21,6 +22,8 @@ constexpr size_t LDS_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
   X(19, 19) X(21, 21) X(23, 23) X(4, 3) X(4, 5) X(6, 4) X(8, 5) X(8, 7) X(8, 9) X(12, 7)  \
   X(12, 9) X(12, 11) X(16, 9) X(16, 11) X(16, 13) X(16, 15) X(24, 13) X(24, 17) X(24, 19) \
   X(32, 17) X(32, 21) X(32, 23) X(33, 33) X(35, 35) X(43, 43) X(64, 33) X(64, 35) X(64, 43)
+// Tiles built for 2D only: the continuous element-centred patches of P_l = 32.
+#define DGMG_FDM_LIST_2D(X) X(41, 41)
 
 template <class T, int DIM>
 int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* scratch, double* part,
@@ -43,6 +46,9 @@ bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
 #define DGMG_CASE(A, B) \
   if (NA == A && NL == B) return true;
   DGMG_FDM_LIST(DGMG_CASE)
+  if constexpr (DIM == 2) {
+    DGMG_FDM_LIST_2D(DGMG_CASE)
+  }
 #undef DGMG_CASE
   return false;
 }
@@ -52,6 +58,9 @@ bool Kern<T, DIM>::fdm_in_lds(int NA, int NL) {
 #define DGMG_CASE(A, B) \
   if (NA == A && NL == B) return !(DIM == 3 && fdm_lds_total<T, A, B, DIM>() > LDS_BYTES);
   DGMG_FDM_LIST(DGMG_CASE)
+  if constexpr (DIM == 2) {
+    DGMG_FDM_LIST_2D(DGMG_CASE)
+  }
 #undef DGMG_CASE
   return false;
 }
@@ -70,6 +79,12 @@ int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, 
   }
   DGMG_FDM_LIST(DGMG_CASE)
 #undef DGMG_CASE
+  if constexpr (DIM == 2) {
+#define DGMG_CASE(A, B) \
+  if (NA == A && NL == B) return fdm_launch_t<T, DIM, A, B>(L, nd, r, out, npx, npy, npz, waves, lat, s);
+    DGMG_FDM_LIST_2D(DGMG_CASE)
+#undef DGMG_CASE
+  }
   return -4;
 }
 
@@ -202,6 +217,32 @@ int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T
       return restrict_ ? transfer_launch_t<T, DIM, F, C, true>(Lf.J, Lf.n_elem, in, out, Lf.active, s) \
                        : transfer_launch_t<T, DIM, F, C, false>(Lf.J, Lf.n_elem, in, out, Lf.active, s); \
   }
+  DGMG_XFER_LIST(DGMG_CASE)
+#undef DGMG_CASE
+  return -4;
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::se_apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* ebuf, hipStream_t s) {
+  switch (L.NP) {
+#define DGMG_CASE(NP) \
+  case NP: return se_apply_launch<T, DIM, NP>(L, mode, x, f, y, ebuf, s);
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return -4;
+  }
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::se_combine(const LevelDev<T>& L, int NA, const T* buf, T* u, bool assign, hipStream_t s) {
+  return se_combine_launch<T, DIM>(L, NA, buf, u, assign, s);
+}
+
+template <class T, int DIM>
+int Kern<T, DIM>::se_transfer(const LevelDev<T>& Lf, const LevelDev<T>& Lc, bool restrict_, const T* in, T* out,
+                              T* ebuf, hipStream_t s) {
+#define DGMG_CASE(F, C) \
+  if (Lf.NP == F && Lf.NPc == C) return se_transfer_launch<T, DIM, F, C>(Lf, Lc, restrict_, in, out, ebuf, s);
   DGMG_XFER_LIST(DGMG_CASE)
 #undef DGMG_CASE
   return -4;

@@ -34,6 +34,7 @@ enum { ECOEF_N = 8, E_TWO_DX = 0, E_HALF_DX, E_CL, E_CNL, E_BL, E_CR, E_CNR, E_B
 template <class T>
 struct DirDev {
   int N = 1, periodic = 0;
+  int nl = 0;  // continuous levels: stored lattice nodes of the direction
   int n_ec = 0, n_fc = 0, nf = 0;
   const T* ecoef = nullptr;  // N * 8 (see ECOEF enum)
   const int* nbr = nullptr;  // N * 2
@@ -54,6 +55,7 @@ struct DirDev {
 template <class T>
 struct LevelDev {
   int dim = 3, P = 1, NP = 2, NO = 0, NPc = 0;
+  int se = 0;  // 1: continuous spectral-element level (lattice vectors)
   int n_elem = 0;
   int64_t n_dof = 0;
   const T* Ls = nullptr;   // NP*NP
@@ -1589,6 +1591,13 @@ struct Kern {
                      int npy, int npz, bool assign, hipStream_t s);
   // tmp: scratch of transfer_big_scratch(n_elem, NP, NPc) elements (3D levels with NP = 33 only)
   static int transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T* out, T* tmp, hipStream_t s);
+  // Continuous spectral-element levels (lattice vectors, kernels_se.hpp).
+  // ebuf: element-major scratch of n_elem * NP^DIM elements.  Modes 0 and 1.
+  static int se_apply(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* ebuf, hipStream_t s);
+  static int se_combine(const LevelDev<T>& L, int NA, const T* buf, T* u, bool assign, hipStream_t s);
+  // ebuf (restriction only): n_elem * NPc^DIM elements
+  static int se_transfer(const LevelDev<T>& Lf, const LevelDev<T>& Lc, bool restrict_, const T* in, T* out,
+                         T* ebuf, hipStream_t s);
 };
 
 }  // namespace dgmg

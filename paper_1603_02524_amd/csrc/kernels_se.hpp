@@ -1,0 +1,389 @@
+// Continuous spectral-element (SE) counterpart (Sec. 4.3): kernels on the
+// global node lattice.
+//
+// Vector layout: per direction d the lattice positions g = m P + i of element
+// m's nodes (neighbours share g = m P); a homogeneous Dirichlet direction
+// stores g = 1 .. N P - 1 at g - 1, a periodic one g mod N P; entries
+// s0 + nl0 (s1 + nl1 s2), direction 1 fastest (nl_d = DirDev::nl).
+//
+// Operator (direct stiffness summation): y = sum_e Q_e^T A_e Q_e x in two
+// launches, the element-local A_e x_e of every element into an element-major
+// buffer (se_elem_kernel), then per lattice node the sum of the copies of the
+// elements sharing it, in a fixed order (se_dss_kernel).  No atomics: the
+// result does not depend on the launch order.
+// Smoother: the element-centred patch solves are the DG ones (fdm_kernel with
+// the continuous tables and lattice offsets); their weighted corrections are
+// summed per lattice node by se_combine_kernel.
+// Transfers: prolongation per element onto the nodes it owns (i_d < P in every
+// direction: each lattice node has exactly one owner); restriction per element
+// with the shared fine nodes weighted by 1 / (number of elements sharing them)
+// into an element-major coarse buffer, then the coarse node sum.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace dgmg {
+
+// Stored index of lattice position g in a direction with N elements of order P
+// (-1: a dropped Dirichlet node).
+__device__ __forceinline__ int se_stored(int g, int P, int N, int periodic) {
+  const int G = N * P;
+  if (periodic) {
+    g %= G;
+    return g < 0 ? g + G : g;
+  }
+  return (g >= 1 && g <= G - 1) ? g - 1 : -1;
+}
+
+template <int NP, int DIM>
+constexpr int se_epb() {
+  return imax(1, 256 / ipow(NP, DIM));
+}
+template <int DIM, int NP>
+inline int se_elem_blocks(int n_elem) {
+  return (n_elem + se_epb<NP, DIM>() - 1) / se_epb<NP, DIM>();
+}
+
+// Lattice strides of the directions of level L.
+template <class T>
+__device__ __forceinline__ void se_strides(const LevelDev<T>& L, int64_t st[3]) {
+  st[0] = 1;
+  st[1] = L.dir[0].nl;
+  st[2] = (int64_t)L.dir[0].nl * L.dir[1].nl;
+}
+
+// Per element of the block and direction: the stored offset of each local node
+// (-1: dropped) into the lattice vector of level L.
+template <class T, int DIM, int NP, int EPB>
+__device__ __forceinline__ void se_elem_offsets(const LevelDev<T>& L, int e0, int ne, int64_t (*off)[3][NP]) {
+  int64_t st[3];
+  se_strides(L, st);
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N, P = NP - 1;
+  for (int q = threadIdx.x; q < ne * DIM * NP; q += blockDim.x) {
+    const int el = q / (DIM * NP), rem = q - el * DIM * NP, d = rem / NP, i = rem - d * NP;
+    const int e = e0 + el;
+    const int md = d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
+    const DirDev<T>& dd = L.dir[d];
+    const int s = se_stored(md * P + i, P, dd.N, dd.periodic);
+    off[el][d][i] = s < 0 ? -1 : s * st[d];
+  }
+  if (DIM == 2)
+    for (int q = threadIdx.x; q < ne; q += blockDim.x) off[q][2][0] = 0;
+}
+
+// w_e = A_e x_e for every element (element-major output, NP^DIM per element):
+// A_e = sum_d (x)_{d' != d} (dx_{d'}/2) diag(rho) (x) (2/dx_d) L^s.
+template <class T, int DIM, int NP>
+__global__ void __launch_bounds__(256) se_elem_kernel(LevelDev<T> L, const T* __restrict__ x, T* __restrict__ w,
+                                                      int nblk) {
+  constexpr int NE = ipow(NP, DIM), EPB = se_epb<NP, DIM>();
+  constexpr int NZ = DIM == 3 ? NP : 1;
+  __shared__ T xs[EPB][NE];
+  __shared__ T sL[NP * NP];
+  __shared__ T srho[NP];
+  __shared__ int64_t off[EPB][3][NP];
+  __shared__ T two[EPB][3], half[EPB][3];
+  const int blk = xcd_block(nblk);
+  if (blk < 0 || inactive(L.active)) return;
+  const int e0 = blk * EPB, ne = imin(EPB, L.n_elem - e0);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < NP * NP; q += nth) sL[q] = L.Ls[q];
+  for (int q = tid; q < NP; q += nth) srho[q] = L.rho[q];
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  for (int q = tid; q < ne * 3; q += nth) {
+    const int el = q / 3, d = q - el * 3, e = e0 + el;
+    if (d >= DIM) {
+      two[el][d] = T(0);
+      half[el][d] = T(1);
+      continue;
+    }
+    const int md = d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
+    two[el][d] = L.dir[d].ecoef[md * ECOEF_N + E_TWO_DX];
+    half[el][d] = L.dir[d].ecoef[md * ECOEF_N + E_HALF_DX];
+  }
+  se_elem_offsets<T, DIM, NP, EPB>(L, e0, ne, off);
+  __syncthreads();
+  for (int q = tid; q < ne * NE; q += nth) {
+    const int el = q / NE, loc = q - el * NE;
+    const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
+    const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
+    const bool ok = (a | b | c) >= 0;
+    const T v = x[ok ? a + b + c : 0];
+    xs[el][loc] = ok ? v : T(0);
+  }
+  __syncthreads();
+  for (int q = tid; q < ne * NE; q += nth) {
+    const int el = q / NE, loc = q - el * NE;
+    const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
+    const T* t = xs[el];
+    T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll 4
+    for (int a = 0; a < NP; ++a) {
+      sx += sL[i * NP + a] * t[(k * NP + j) * NP + a];
+      sy += sL[j * NP + a] * t[(k * NP + a) * NP + i];
+      if (DIM == 3) sz += sL[k * NP + a] * t[(a * NP + j) * NP + i];
+    }
+    const T mx = half[el][0] * srho[i], my = half[el][1] * srho[j];
+    const T mz = DIM == 3 ? half[el][2] * srho[k] : T(1);
+    T v = two[el][0] * sx * my * mz + mx * two[el][1] * sy * mz;
+    if (DIM == 3) v += mx * my * two[el][2] * sz;
+    w[(int64_t)(e0 + el) * NE + loc] = v;
+  }
+  (void)NZ;
+}
+
+// Lattice node q of level L: per direction the (element, local node) pairs of
+// the elements sharing it (two at an element boundary, else one).
+template <class T, int DIM>
+__device__ __forceinline__ void se_node_owners(const LevelDev<T>& L, int64_t q, int cnt[3], int em[3][2],
+                                               int lo[3][2]) {
+  const int P = L.P;
+  int64_t rest = q;
+  for (int d = 0; d < 3; ++d) {
+    cnt[d] = 1;
+    em[d][0] = 0;
+    lo[d][0] = 0;
+    if (d >= DIM) continue;
+    const DirDev<T>& dd = L.dir[d];
+    const int s = (int)(rest % dd.nl);
+    rest /= dd.nl;
+    const int g = dd.periodic ? s : s + 1;
+    const int m = g / P, i = g - m * P;
+    if (i != 0) {
+      em[d][0] = m;
+      lo[d][0] = i;
+    } else {  // shared by element m - 1 (its node P) and element m (its node 0)
+      em[d][0] = m == 0 ? dd.N - 1 : m - 1;  // m = 0 only on a periodic direction
+      lo[d][0] = P;
+      em[d][1] = m;
+      lo[d][1] = 0;
+      cnt[d] = 2;
+    }
+  }
+}
+
+// y = sum of the element copies (MODE 0), y = f - sum (MODE 1).
+template <class T, int DIM, int NP>
+__global__ void __launch_bounds__(256) se_dss_kernel(LevelDev<T> L, const T* __restrict__ w,
+                                                     const T* __restrict__ f, T* __restrict__ y, int mode) {
+  if (inactive(L.active)) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.n_dof) return;
+  constexpr int NE = ipow(NP, DIM);
+  int cnt[3], em[3][2], lo[3][2];
+  se_node_owners<T, DIM>(L, q, cnt, em, lo);
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  T s = T(0);
+  for (int c = 0; c < cnt[2]; ++c)
+    for (int b = 0; b < cnt[1]; ++b)
+      for (int a = 0; a < cnt[0]; ++a) {
+        const int64_t e = em[0][a] + (int64_t)N1 * (em[1][b] + (int64_t)N2 * em[2][c]);
+        s += w[e * NE + (lo[2][c] * NP + lo[1][b]) * NP + lo[0][a]];
+      }
+  y[q] = mode == 1 ? f[q] - s : s;
+}
+
+// u (+)= sum over the element-centred patches covering each lattice node of
+// their weighted corrections (buf: one NA^DIM tile per patch, patch index
+// m1 + N1 (m2 + N2 m3), tile position t1 + NA (t2 + NA t3), patch m's tile
+// starting at lattice position m P - N_O).  Sum order: direction 3, 2, 1
+// candidates, each in increasing patch index.
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, const T* __restrict__ buf,
+                                                         T* __restrict__ u, int assign) {
+  if (inactive(L.active)) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.n_dof) return;
+  const int P = L.P, NO = L.NO;
+  int cnt[3], pm[3][3], tp[3][3];
+  int64_t rest = q;
+  for (int d = 0; d < 3; ++d) {
+    cnt[d] = 0;
+    if (d >= DIM) {
+      cnt[d] = 1;
+      pm[d][0] = 0;
+      tp[d][0] = 0;
+      continue;
+    }
+    const DirDev<T>& dd = L.dir[d];
+    const int s = (int)(rest % dd.nl);
+    rest /= dd.nl;
+    const int g = dd.periodic ? s : s + 1;
+    const int m0 = g / P;
+    for (int k = -2; k <= 1; ++k) {
+      const int m = m0 + k;
+      const int t = g - (m * P - NO);
+      if (t < 0 || t >= NA || cnt[d] >= 3) continue;
+      if (!dd.periodic && (m < 0 || m >= dd.N)) continue;
+      pm[d][cnt[d]] = ((m % dd.N) + dd.N) % dd.N;
+      tp[d][cnt[d]] = t;
+      ++cnt[d];
+    }
+  }
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  const int64_t TS = DIM == 3 ? (int64_t)NA * NA * NA : (int64_t)NA * NA;
+  T s = T(0);
+  for (int c = 0; c < cnt[2]; ++c)
+    for (int b = 0; b < cnt[1]; ++b)
+      for (int a = 0; a < cnt[0]; ++a) {
+        const int64_t pid = pm[0][a] + (int64_t)N1 * (pm[1][b] + (int64_t)N2 * pm[2][c]);
+        s += buf[pid * TS + ((int64_t)tp[2][c] * NA + tp[1][b]) * NA + tp[0][a]];
+      }
+  u[q] = assign ? s : u[q] + s;
+}
+
+// One contraction pass of the element transfers along direction D: src has
+// NOUT points along directions < D and NIN along the others; dst maps
+// direction D to NOUT points with M (row-major, MT = false: dst_i = sum_a
+// M[i][a] src_a with M NOUT x NIN; MT = true: dst_i = sum_a M[a][i] src_a with
+// M NIN x NOUT).
+template <class T, int DIM, int NIN, int NOUT, int D, bool MT>
+__device__ __forceinline__ void se_xpass(const T* __restrict__ M, const T* __restrict__ src, T* __restrict__ dst) {
+  constexpr int n0 = D > 0 ? NOUT : NIN, n1 = DIM >= 2 ? (D > 1 ? NOUT : NIN) : 1;
+  constexpr int m0 = D == 0 ? NOUT : n0;
+  constexpr int m1 = D == 1 ? NOUT : n1;
+  constexpr int m2 = DIM == 3 ? (D == 2 ? NOUT : NIN) : 1;
+  constexpr int SK = D == 0 ? 1 : (D == 1 ? n0 : n0 * n1);
+  for (int q = threadIdx.x; q < m0 * m1 * m2; q += blockDim.x) {
+    const int i0 = q % m0, i1 = (q / m0) % m1, i2 = q / (m0 * m1);
+    const int io = D == 0 ? i0 : (D == 1 ? i1 : i2);
+    const int base = (D == 0 ? 0 : i0) + (D == 1 ? 0 : i1) * n0 + (D == 2 ? 0 : i2) * n0 * n1;
+    T s = T(0);
+#pragma unroll 4
+    for (int a = 0; a < NIN; ++a) s += (MT ? M[a * NOUT + io] : M[io * NIN + a]) * src[base + a * SK];
+    dst[q] = s;
+  }
+}
+
+// u_f += I u_c on the fine nodes each element owns.  Lf: the fine level (J is
+// NPF x NPC); Lc: the coarse level.
+template <class T, int DIM, int NPF, int NPC>
+__global__ void __launch_bounds__(256) se_prolong_kernel(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ uc,
+                                                         T* __restrict__ uf, int nblk) {
+  constexpr int NEF = ipow(NPF, DIM), NEC = ipow(NPC, DIM);
+  __shared__ T ta[NEF], tb[NEF];
+  __shared__ T sJ[NPF * NPC];
+  __shared__ int64_t offc[1][3][NPC];
+  __shared__ int64_t offf[1][3][NPF];
+  const int e = xcd_block(nblk);
+  if (e < 0 || inactive(Lf.active)) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = Lf.J[q];
+  se_elem_offsets<T, DIM, NPC, 1>(Lc, e, 1, offc);
+  se_elem_offsets<T, DIM, NPF, 1>(Lf, e, 1, offf);
+  __syncthreads();
+  for (int q = tid; q < NEC; q += nth) {
+    const int i = q % NPC, j = (q / NPC) % NPC, k = DIM == 3 ? q / (NPC * NPC) : 0;
+    const int64_t a = offc[0][0][i], b = offc[0][1][j], c = offc[0][2][k];
+    const bool ok = (a | b | c) >= 0;
+    const T v = uc[ok ? a + b + c : 0];
+    ta[q] = ok ? v : T(0);
+  }
+  __syncthreads();
+  se_xpass<T, DIM, NPC, NPF, 0, false>(sJ, ta, tb);
+  __syncthreads();
+  se_xpass<T, DIM, NPC, NPF, 1, false>(sJ, tb, ta);
+  __syncthreads();
+  const T* res = ta;
+  if constexpr (DIM == 3) {
+    se_xpass<T, DIM, NPC, NPF, 2, false>(sJ, ta, tb);
+    __syncthreads();
+    res = tb;
+  }
+  constexpr int PF = NPF - 1;
+  for (int q = tid; q < NEF; q += nth) {
+    const int i = q % NPF, j = (q / NPF) % NPF, k = DIM == 3 ? q / (NPF * NPF) : 0;
+    if (i == PF || j == PF || (DIM == 3 && k == PF)) continue;  // owned by the next element
+    const int64_t a = offf[0][0][i], b = offf[0][1][j], c = offf[0][2][k];
+    if ((a | b | c) < 0) continue;
+    uf[a + b + c] += res[q];
+  }
+}
+
+// wc_e = (J^T (x) J^T (x) J^T) (W r_f,e) per element (element-major coarse
+// output): W halves a fine node per direction in which it lies on an element
+// boundary (shared by two elements; dropped Dirichlet nodes read 0).
+template <class T, int DIM, int NPF, int NPC>
+__global__ void __launch_bounds__(256) se_restrict_kernel(LevelDev<T> Lf, const T* __restrict__ rf,
+                                                          T* __restrict__ wc, int nblk) {
+  constexpr int NEF = ipow(NPF, DIM), NEC = ipow(NPC, DIM);
+  __shared__ T ta[NEF], tb[NEF];
+  __shared__ T sJ[NPF * NPC];
+  __shared__ int64_t offf[1][3][NPF];
+  const int e = xcd_block(nblk);
+  if (e < 0 || inactive(Lf.active)) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int q = tid; q < NPF * NPC; q += nth) sJ[q] = Lf.J[q];
+  se_elem_offsets<T, DIM, NPF, 1>(Lf, e, 1, offf);
+  __syncthreads();
+  constexpr int PF = NPF - 1;
+  for (int q = tid; q < NEF; q += nth) {
+    const int i = q % NPF, j = (q / NPF) % NPF, k = DIM == 3 ? q / (NPF * NPF) : 0;
+    const int64_t a = offf[0][0][i], b = offf[0][1][j], c = offf[0][2][k];
+    const bool ok = (a | b | c) >= 0;
+    T v = rf[ok ? a + b + c : 0];
+    T wgt = T(1);
+    if (i == 0 || i == PF) wgt *= T(0.5);
+    if (j == 0 || j == PF) wgt *= T(0.5);
+    if (DIM == 3 && (k == 0 || k == PF)) wgt *= T(0.5);
+    ta[q] = ok ? wgt * v : T(0);
+  }
+  __syncthreads();
+  se_xpass<T, DIM, NPF, NPC, 0, true>(sJ, ta, tb);
+  __syncthreads();
+  se_xpass<T, DIM, NPF, NPC, 1, true>(sJ, tb, ta);
+  __syncthreads();
+  const T* res = ta;
+  if constexpr (DIM == 3) {
+    se_xpass<T, DIM, NPF, NPC, 2, true>(sJ, ta, tb);
+    __syncthreads();
+    res = tb;
+  }
+  for (int q = tid; q < NEC; q += nth) wc[(int64_t)e * NEC + q] = res[q];
+}
+
+inline unsigned se_node_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ------------------------------------------------------------------ launchers
+template <class T, int DIM, int NP>
+int se_apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y, T* ebuf, hipStream_t s) {
+  if constexpr (DIM == 3 && NP > 17) {
+    return -4;  // element tiles beyond LDS
+  } else {
+    if (mode != 0 && mode != 1) return -4;
+    const int nb = se_elem_blocks<DIM, NP>(L.n_elem);
+    hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP>), dim3(xcd_grid(nb)), dim3(256), 0, s, L, x, ebuf, nb);
+    hipLaunchKernelGGL((se_dss_kernel<T, DIM, NP>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L,
+                       (const T*)ebuf, f, y, mode);
+    return 0;
+  }
+}
+
+template <class T, int DIM>
+int se_combine_launch(const LevelDev<T>& L, int NA, const T* buf, T* u, bool assign, hipStream_t s) {
+  hipLaunchKernelGGL((se_combine_kernel<T, DIM>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L, NA, buf, u,
+                     assign ? 1 : 0);
+  return 0;
+}
+
+template <class T, int DIM, int NPF, int NPC>
+int se_transfer_launch(const LevelDev<T>& Lf, const LevelDev<T>& Lc, bool restrict_, const T* in, T* out, T* ebuf,
+                       hipStream_t s) {
+  if constexpr (DIM == 3 && NPF > 17) {
+    return -4;
+  } else {
+    const int nb = Lf.n_elem;
+    if (restrict_) {
+      hipLaunchKernelGGL((se_restrict_kernel<T, DIM, NPF, NPC>), dim3(xcd_grid(nb)), dim3(256), 0, s, Lf, in, ebuf,
+                         nb);
+      hipLaunchKernelGGL((se_dss_kernel<T, DIM, NPC>), dim3(se_node_blocks(Lc.n_dof)), dim3(256), 0, s, Lc,
+                         (const T*)ebuf, (const T*)nullptr, out, 0);
+    } else {
+      hipLaunchKernelGGL((se_prolong_kernel<T, DIM, NPF, NPC>), dim3(xcd_grid(nb)), dim3(256), 0, s, Lf, Lc, in,
+                         out, nb);
+    }
+    return 0;
+  }
+}
+
+}  // namespace dgmg

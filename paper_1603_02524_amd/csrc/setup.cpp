@@ -275,6 +275,32 @@ void patch_tables(int n, int start, int G, bool periodic, const std::vector<doub
   for (int a = 0; a < k; ++a) w[pos[a]] = wfn(start + pos[a]);
 }
 
+// Continuous spectral-element direction data (Sec. 4.3 counterpart): the
+// assembled 1D stiffness L (dense nl x nl) and lumped mass of the stored
+// lattice nodes (direct stiffness summation of (2/dx) L^s and (dx/2) rho).
+void se_global_1d(int P, const std::vector<double>& Ls, const std::vector<double>& rho, const Dir1D& d,
+                  std::vector<double>& L, std::vector<double>& mvec) {
+  const int NP = P + 1, G = d.nl, NT = d.N * P;
+  L.assign((size_t)G * G, 0.0);
+  mvec.assign(G, 0.0);
+  auto stored = [&](int g) {
+    if (d.periodic) return ((g % NT) + NT) % NT;
+    return (g >= 1 && g <= NT - 1) ? g - 1 : -1;
+  };
+  for (int m = 0; m < d.N; ++m) {
+    const double h = d.dx[m];
+    for (int i = 0; i < NP; ++i) {
+      const int a = stored(m * P + i);
+      if (a < 0) continue;
+      mvec[a] += 0.5 * h * rho[i];
+      for (int k = 0; k < NP; ++k) {
+        const int b = stored(m * P + k);
+        if (b >= 0) L[(size_t)a * G + b] += (2.0 / h) * Ls[i * NP + k];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels) {
@@ -288,10 +314,16 @@ std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels) 
     lv.P = P;
     lv.NP = NP;
     lv.dim = sp.dim;
-    lv.NO = l == 0 ? 0 : overlap_rule(P, sp.overlap);
-    if (lv.NO < 0 || lv.NO > P) {
+    const bool se = sp.disc == 1;
+    lv.se = se;
+    // continuous subdomains take N_O node layers of each neighbour beyond the
+    // shared boundary node: the DG rule's value minus one (the DG subdomain
+    // counts the coinciding neighbour node as a layer of its own)
+    lv.NO = l == 0 ? 0 : overlap_rule(P, sp.overlap) - (se ? 1 : 0);
+    if (lv.NO < 0 || lv.NO > P || (se && l > 0 && lv.NO + 1 > P)) {
       std::ostringstream os;
-      os << "overlap N_O=" << lv.NO << " outside [0, P_l=" << P << "]";
+      if (se && lv.NO < 0) os << "continuous subdomains need the DG overlap N_O >= 1 on level P_l=" << P;
+      else os << "overlap N_O=" << lv.NO << " outside [0, P_l=" << P << (se ? " - 1]" : "]");
       return os.str();
     }
     std::vector<double> eta;
@@ -308,6 +340,10 @@ std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels) 
     for (int d = 0; d < sp.dim; ++d) lv.n_elem *= sp.n[d];
     lv.n_dof = lv.n_elem;
     for (int d = 0; d < sp.dim; ++d) lv.n_dof *= NP;
+    if (se) {
+      lv.n_dof = 1;
+      for (int d = 0; d < sp.dim; ++d) lv.n_dof *= sp.periodic[d] ? sp.n[d] * P : sp.n[d] * P - 1;
+    }
     if (l > 0) {  // embedded interpolation from the coarser level (barycentric Lagrange)
       const int Pc = orders[l - 1], NPc = Pc + 1;
       std::vector<double> ec, rc;
@@ -338,6 +374,50 @@ std::string build_levels(const SetupParams& sp, std::vector<LevelHost>& levels) 
       dd.dx = sp.dx[d];
       const double beta = sp.flux == 1 ? sp.beta[d] : 0.0;
       element_coefficients(P, lv.rho, beta, sp.mu_star, dd);
+      if (se) {
+        dd.nl = dd.periodic ? dd.N * P : dd.N * P - 1;
+        if (dd.nl < 1) return "a continuous Dirichlet direction needs at least one interior node";
+        std::vector<double> L, mvec;
+        se_global_1d(P, lv.Ls, lv.rho, dd, L, mvec);
+        const int G = dd.nl;
+        if (l == 0) {
+          dd.G = G;
+          gen_eigen(G, L, mvec, dd.S_glob, dd.lam_glob);
+          dd.null_mode = -1;
+          if (dd.periodic) {
+            int imin = 0;
+            for (int j = 0; j < G; ++j)
+              if (std::fabs(dd.lam_glob[j]) < std::fabs(dd.lam_glob[imin])) imin = j;
+            dd.null_mode = imin;
+            dd.lam_glob[imin] = 0.0;
+          }
+          continue;
+        }
+        // element-centred subdomains: tile position t <-> lattice position m P - N_O + t
+        const int NO = lv.NO;
+        dd.n_ec = NP + 2 * NO;
+        const int n = dd.n_ec;
+        dd.S_ec.assign((size_t)dd.N * n * n, 0.0);
+        dd.lam_ec.assign(dd.N * n, 0.0);
+        dd.w_ec.assign(dd.N * n, 0.0);
+        const double dxo = eta[NO + 1] + 1.0;  // distance to the nearest excluded node layer
+        const int shift = dd.periodic ? 0 : 1;  // stored index = lattice position - shift
+        for (int m = 0; m < dd.N; ++m) {
+          const bool lb = !dd.periodic && m == 0, rb = !dd.periodic && m == dd.N - 1;
+          auto wfn = [&](int gs) {
+            const int g = gs + shift;
+            int mm = (int)std::floor((double)g / P);
+            int i = g - mm * P;
+            double xh = eta[i] + 2.0 * (mm - m);
+            double a = lb ? 1.0 : phi((1.0 + xh) / dxo, sp.weighting);
+            double b = rb ? 1.0 : phi((1.0 - xh) / dxo, sp.weighting);
+            return 0.5 * (a + b);
+          };
+          patch_tables(n, m * P - NO - shift, G, dd.periodic, L, mvec, wfn, &dd.S_ec[(size_t)m * n * n],
+                       &dd.lam_ec[m * n], &dd.w_ec[m * n]);
+        }
+        continue;
+      }
       std::vector<double> L, mvec(dd.N * NP);
       global_L(P, lv.Ls, lv.D, dd, L);
       for (int m = 0; m < dd.N; ++m)

@@ -28,6 +28,7 @@ enum ECoef {
 struct Dir1D {
   int N = 0;
   bool periodic = false;
+  int nl = 0;  // continuous levels: stored lattice nodes (N P - 1 Dirichlet, N P periodic)
   std::vector<double> dx;
   std::vector<double> ecoef;  // N * EC_COUNT
   std::vector<int> nbr;       // N * 2: left / right neighbour element, -1 at a Dirichlet face
@@ -45,6 +46,7 @@ struct Dir1D {
 
 struct LevelHost {
   int P = 1, NP = 2, NO = 0, dim = 3;
+  bool se = false;  // continuous spectral-element level
   int64_t n_elem = 0, n_dof = 0;
   std::vector<double> rho, Ls, D;  // NP, NP*NP (row-major), NP*NP (D[i*NP+k] = phi_k'(eta_i))
   std::vector<double> J;           // NP x NPc interpolation from the next coarser level (row-major)
@@ -64,6 +66,7 @@ struct SetupParams {
   int smoother = 1;
   int overlap = -1;
   int weighting = 0;
+  int disc = 0;  // 0: DG; 1: the continuous spectral-element counterpart (element-centred smoother only)
 };
 
 // Builds all levels (index 0 = coarsest, P = 1).  Returns an empty string on

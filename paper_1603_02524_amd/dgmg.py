@@ -22,6 +22,7 @@ F64, F32 = 0, 1
 _FLUX = {"ip": 0, "ldg": 1}
 _SMOOTHER = {"EA": 0, "FA": 1, "EM": 2, "FM": 3}
 _ORDER = {"lex": 0, "colour": 1}
+_DISC = {"dg": 0, "se": 1}
 _WEIGHT = {"quintic": 0, "cubic": 1, "arith": 2, "none": 3}
 _VCYCLE = {"classical": 0, "variable": 1}
 _PREC = {"fp64": 0, "mixed": 1}
@@ -36,7 +37,7 @@ class DgmgOpts(ctypes.Structure):
     _fields_ = [("P", c_int), ("flux", c_int), ("beta", c_double * 3), ("mu_star", c_double),
                 ("smoother", c_int), ("overlap", c_int), ("weighting", c_int), ("vcycle", c_int),
                 ("ns_pre", c_int), ("ns_post", c_int), ("precision", c_int), ("max_iter", c_int),
-                ("order", c_int)]
+                ("order", c_int), ("disc", c_int)]
 
 
 class DgmgStats(ctypes.Structure):
@@ -162,6 +163,7 @@ def make_structs(grid, method, max_iter: int = 100):
     o.precision = _PREC[method.precision]
     o.max_iter = int(max_iter)
     o.order = _ORDER[getattr(method, "order", "lex")]
+    o.disc = _DISC[getattr(method, "disc", "dg")]
     return g, o, keep
 
 
@@ -248,7 +250,11 @@ class Solver:
 
     def node_coords(self, level, d):
         P, _, _ = self.level_info(level)
-        out = np.zeros(len(self.grid.dx[d]) * (P + 1))
+        N = len(self.grid.dx[d])
+        if getattr(self.method, "disc", "dg") == "se":  # stored lattice nodes
+            out = np.zeros(N * P - (0 if self.grid.periodic[d] else 1))
+        else:
+            out = np.zeros(N * (P + 1))
         self._check(self.lib.dgmg_node_coords(self.h, level, d, out.ctypes.data_as(POINTER(c_double))))
         return out
 

@@ -36,6 +36,14 @@ class Grid:
     def n_dof(self, P: int) -> int:
         return self.n_elem * (P + 1) ** self.dim
 
+    def n_lattice(self, P: int) -> int:
+        """Unknowns of the continuous counterpart: per direction the N P element
+        boundary and interior node positions, less the two ends when Dirichlet."""
+        out = 1
+        for d in range(self.dim):
+            out *= len(self.dx[d]) * P - (0 if self.periodic[d] else 1)
+        return out
+
     def aspect_ratio(self) -> float:
         """Largest ratio of two element sizes within any single element."""
         if self.dim == 1:
@@ -56,7 +64,9 @@ class Method:
     "quintic", "cubic", "arith", "none" (additive smoothers only); vcycle:
     "classical" or "variable"; precision: "fp64" or "mixed"; order: subdomain
     order of the multiplicative smoothers, "lex" (lexicographic, direction 1
-    fastest) or "colour" (colour classes of mutually independent subdomains).
+    fastest) or "colour" (colour classes of mutually independent subdomains);
+    disc: "dg" or "se" (the continuous spectral-element counterpart, with the
+    element-centred additive smoother).
     """
 
     P: int
@@ -71,6 +81,7 @@ class Method:
     precision: str = "fp64"
     krylov: bool = True
     order: str = "lex"
+    disc: str = "dg"
 
 
 @dataclass
@@ -84,6 +95,8 @@ class Workload:
 
     @property
     def n_dof(self) -> int:
+        if self.method.disc == "se":
+            return self.grid.n_lattice(self.method.P)
         return self.grid.n_dof(self.method.P)
 
 

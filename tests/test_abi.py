@@ -34,7 +34,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(D.DgmgStats) == 4 + 4 + 8 * 3 + 8 * 256 + 8 + 4 + 4  # r_true, replacements, tail padding
     # int dim; int n_elem[3]; const double* dx[3] (8-aligned at 16); int periodic[3]; tail pad
     assert ctypes.sizeof(D.DgmgGrid) == 56
-    assert ctypes.sizeof(D.DgmgOpts) == 4 + 4 + 24 + 8 + 4 * 9 + 4  # order; tail padding to 8
+    assert ctypes.sizeof(D.DgmgOpts) == 4 + 4 + 24 + 8 + 4 * 10  # ... order, disc
 
 
 def test_defaults():
@@ -214,3 +214,56 @@ def test_batch_plan_host_side():
         assert _plan(lib, b)[0] == 0
     finally:
         lib.dgmg_batch_destroy(b)
+
+
+@pytest.mark.parametrize("dim,n,periodic,P", [(2, (5, 3), False, 4), (2, (4, 3), True, 32), (3, (3, 2, 3), (True, False, False), 6),
+                                              (3, (2, 2, 2), False, 16), (3, (3, 4, 3), True, 2)])
+def test_continuous_setup_matches_oracle_lattice(dim, n, periodic, P):
+    """Continuous handles (host only): level sizes, overlaps and lattice node
+    coordinates equal the oracle's."""
+    from oracle import se
+    lib = D.load_library()
+    rng = np.random.default_rng(3)
+    per = periodic if isinstance(periodic, tuple) else (periodic,) * dim
+    g = synth.Grid(dim, tuple(rng.uniform(0.4, 1.6, n[d]) for d in range(dim)), per)
+    m = synth.Method(P=P, smoother="EA", disc="se")
+    h, keep = D.setup_handle(g, m)
+    try:
+        from oracle import multigrid as mg
+        orders = mg.level_orders(P)
+        assert lib.dgmg_num_levels(h) == len(orders)
+        for l, Pl in enumerate(orders):
+            Pc, no, nd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+            assert lib.dgmg_level_info(h, l, ctypes.byref(Pc), ctypes.byref(no), ctypes.byref(nd)) == 0
+            assert Pc.value == Pl and nd.value == se.n_dof(g, Pl) == g.n_lattice(Pl)
+            if l > 0:
+                assert no.value == se.se_overlap(Pl, "level")
+            for d in range(dim):
+                ref = se.node_coords_1d(g.dx[d], Pl, per[d])
+                x = np.zeros(len(ref))
+                assert lib.dgmg_node_coords(h, l, d, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+                assert np.allclose(x, ref, rtol=0, atol=1e-14)
+    finally:
+        lib.dgmg_destroy(h)
+
+
+def test_continuous_unsupported_configurations_are_rejected():
+    g = synth.uniform_grid(3, 2, 1.0, False)
+    for m in (synth.Method(P=4, smoother="FA", disc="se"), synth.Method(P=32, smoother="EA", disc="se"),
+              synth.Method(P=4, smoother="EA", overlap="zero", disc="se"),
+              synth.Method(P=4, smoother="EM", disc="se")):
+        with pytest.raises(D.DgmgError):
+            D.setup_handle(g, m)
+    # a Dirichlet direction of one element has no coarse unknowns
+    g1 = synth.Grid(3, (np.ones(1), np.ones(2), np.ones(2)), (False,) * 3)
+    with pytest.raises(D.DgmgError):
+        D.setup_handle(g1, synth.Method(P=4, smoother="EA", disc="se"))
+    # batches take DG grids only
+    lib = D.load_library()
+    probs = [(g, synth.Method(P=4, smoother="EA", disc="se"))]
+    grids = (D.DgmgGrid * 1)()
+    opts = (D.DgmgOpts * 1)()
+    gg, oo, kk = D.make_structs(*probs[0])
+    grids[0], opts[0] = gg, oo
+    b = ctypes.c_void_p()
+    assert lib.dgmg_batch_setup(1, grids, opts, ctypes.byref(b)) == D.DgmgError(-4, "").code

@@ -1,0 +1,218 @@
+"""GPU parity of the continuous spectral-element counterpart (Sec. 4.3) against
+the oracle's SE hierarchy: operator at every level, mass, transfers, exact coarse
+solve, smoother, V-cycle and MGCG, FP64 and mixed precision.  Library and oracle
+share the lattice layout (direction 1 fastest), so vectors compare as they are.
+
+Tolerances as for the DG path: FP64 kernels within 1e-12 (operator, transfers)
+or 1e-11 (smoother, coarse solve) relative, the V-cycle within 1e-10; MGCG by
+check_solve_parity (same iterations as rounding allows, x within 1e-10) and the
+true residual within tol ||f|| plus its evaluation rounding; FP32 kernels within
+a bound derived from float rounding."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import check_solve_parity, rand_grid, residual_bound
+from oracle import se
+
+torch = pytest.importorskip("torch")
+from paper_1603_02524_amd import dgmg as D  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# (id, grid kwargs, method kwargs): ragged element counts, every dimension and
+# boundary kind, orders through the 2D-only P = 32 tile
+SE_CASES = [
+    ("se_2d_dir_p4", dict(dim=2, n=(5, 3), seed=31), dict(P=4)),
+    ("se_2d_per_p8", dict(dim=2, n=(4, 3), periodic=True, seed=32), dict(P=8)),
+    ("se_2d_dir_p12_cubic", dict(dim=2, n=(2, 3), seed=38), dict(P=12, weighting="cubic")),
+    ("se_2d_per_p32", dict(dim=2, n=(3, 3), periodic=True, seed=36), dict(P=32)),
+    ("se_3d_dir_p8", dict(dim=3, n=(3, 2, 3), seed=33), dict(P=8)),
+    ("se_3d_mixed_p6", dict(dim=3, n=(3, 2, 3), periodic=(True, False, False), seed=34), dict(P=6)),
+    ("se_3d_dir_p16", dict(dim=3, n=(2, 2, 2), seed=35), dict(P=16)),
+    ("se_3d_per_p2", dict(dim=3, n=(3, 4, 3), periodic=True, seed=37), dict(P=2)),
+    ("se_3d_dir_p4_overlap2", dict(dim=3, n=(2, 3, 2), seed=39), dict(P=4, overlap=2)),
+]
+IDS = [c[0] for c in SE_CASES]
+
+
+def se_case(cid):
+    for c in SE_CASES:
+        if c[0] == cid:
+            return rand_grid(**c[1]), synth.Method(smoother="EA", disc="se", **c[2])
+    raise KeyError(cid)
+
+
+def _dev(a, dtype=None):
+    return torch.tensor(np.asarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", params=IDS)
+def pair(request):
+    g, m = se_case(request.param)
+    print(f"[case {request.param}]", flush=True)
+    S = D.Solver(g, m, max_iter=200)
+    H = se.SEHierarchy(g, m)
+    yield request.param, g, m, S, H
+    S.close()
+
+
+def test_level_sizes_and_coordinates(pair):
+    cid, g, m, S, H = pair
+    assert S.num_levels == len(H.orders)
+    for l, P in enumerate(H.orders):
+        assert S.n_dof(l) == se.n_dof(g, P)
+        for d in range(g.dim):
+            assert np.allclose(S.node_coords(l, d), se.node_coords_1d(g.dx[d], P, g.periodic[d]), atol=1e-14)
+
+
+def test_apply_all_levels_fp64(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(41)
+    for l in range(H.L + 1):
+        A = H.levels[l].A
+        x = rng.standard_normal(A.shape[0])
+        y = _host(S.apply(l, _dev(x)))
+        assert _rel(y, A @ x) < 1e-12, (cid, l)
+
+
+def test_apply_fp32(pair):
+    """FP32: error bounded by float rounding of |A||x| (a few ulps of the row sums)."""
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(42)
+    A = H.levels[-1].A
+    x = rng.standard_normal(A.shape[0]).astype(np.float32).astype(np.float64)
+    y = _host(S.apply(H.L, _dev(x, torch.float32)))
+    bound = 64 * np.finfo(np.float32).eps * (abs(A) @ np.abs(x))
+    assert np.all(np.abs(y - A @ x) <= bound + 1e-30), cid
+
+
+def test_residual_and_mass_fp64(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(43)
+    A = H.levels[-1].A
+    x, f = rng.standard_normal((2, A.shape[0]))
+    r = _host(S.residual(H.L, _dev(f), _dev(x)))
+    assert _rel(r, f - A @ x) < 1e-12
+    gm = _host(S.mass(_dev(f)))
+    assert _rel(gm, se.mass_vector(g, m.P) * f) < 1e-14
+
+
+def test_transfers(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(44)
+    for l in range(1, H.L + 1):
+        nf, nc = H.levels[l].A.shape[0], H.levels[l - 1].A.shape[0]
+        rf, uf = rng.standard_normal((2, nf))
+        uc = rng.standard_normal(nc)
+        fc = _host(S.restrict(l, _dev(rf)))
+        assert _rel(fc, H.restrict(l, rf)) < 1e-13, (cid, l)
+        ufd = _dev(uf)
+        S.prolong(l, _dev(uc), ufd)
+        assert _rel(_host(ufd), uf + H.prolong(l, uc)) < 1e-13, (cid, l)
+
+
+def test_coarse_solve_exact(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(45)
+    f = rng.standard_normal(H.levels[0].A.shape[0])
+    if all(g.periodic):
+        f -= f.mean()
+    ref = H.coarse_solve(f)
+    assert _rel(_host(S.coarse_solve(_dev(f))), ref) < 1e-11, cid
+    assert _rel(_host(S.coarse_solve(_dev(f, torch.float32))), ref) < 1e-5
+
+
+def test_smooth_one_step_fp64(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(46)
+    for l in range(1, H.L + 1):
+        n = H.levels[l].A.shape[0]
+        u, f = rng.standard_normal((2, n))
+        ref = H.smooth(l, u, f, 1)
+        ud = _dev(u)
+        S.smooth(l, ud, _dev(f), 1)
+        assert _rel(_host(ud), ref) < 1e-11, (cid, l)
+        ud = _dev(u)
+        S.sweep(l, ud, _dev(f), -1)
+        assert _rel(_host(ud), ref) < 1e-11, (cid, l)
+
+
+def test_smooth_two_steps_fp32(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(47)
+    n = H.levels[-1].A.shape[0]
+    u, f = rng.standard_normal((2, n))
+    ref = H.smooth(H.L, u, f, 2)
+    ud = _dev(u, torch.float32)
+    S.smooth(H.L, ud, _dev(f, torch.float32), 2)
+    assert _rel(_host(ud), ref) < 5e-4, cid
+
+
+def test_face_centred_sweep_rejected(pair):
+    cid, g, m, S, H = pair
+    with pytest.raises(D.DgmgError):
+        S.sweep(H.L, _dev(np.zeros(S.n_dof())), _dev(np.zeros(S.n_dof())), 0)
+
+
+def test_vcycle_fp64(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(48)
+    r = rng.standard_normal(H.levels[-1].A.shape[0])
+    if all(g.periodic):
+        r -= r.mean()
+    ref = H.vcycle(np.zeros_like(r), r)
+    assert _rel(_host(S.vcycle(_dev(r))), ref) < 1e-10, cid
+
+
+def test_solve_matches_oracle_fp64(pair):
+    cid, g, m, S, H = pair
+    rng = np.random.default_rng(49)
+    A = H.levels[-1].A
+    f = rng.uniform(-1, 1, A.shape[0])
+    r = rng.standard_normal(A.shape[0])
+    if all(g.periodic):
+        f -= f.mean()
+        r -= r.mean()
+    z_ref = H.vcycle(np.zeros_like(r), r)
+    z_gap = np.linalg.norm(_host(S.vcycle(_dev(r))) - z_ref) / np.linalg.norm(z_ref)
+    x = _dev(np.zeros(A.shape[0]))
+    st = S.solve(_dev(f), x, tol=1e-10)
+    assert st["converged"]
+    xs = _host(x)
+    check_solve_parity(H, f, st, xs, z_gap=z_gap, label=cid)
+    assert np.linalg.norm(f - A @ xs) <= residual_bound(A, f, xs)
+    assert st["r_true"] <= 1e-10 * st["r0"]
+
+
+@pytest.mark.parametrize("cid", ["se_3d_dir_p8", "se_2d_per_p8", "se_3d_mixed_p6"])
+def test_mixed_precision_solve(cid):
+    """FP32 V-cycle inside FP64 PCG reaches the same 1e-10 true residual."""
+    from oracle import multigrid as mg
+    g, m = se_case(cid)
+    m.precision = "mixed"
+    S = D.Solver(g, m, max_iter=60)
+    H = se.SEHierarchy(g, m)
+    A = H.levels[-1].A
+    rng = np.random.default_rng(50)
+    f = rng.uniform(-1, 1, A.shape[0])
+    if all(g.periodic):
+        f -= f.mean()
+    ref = mg.mgcg(H, f, np.zeros_like(f), tol=1e-10, i_max=60)
+    x = _dev(np.zeros(A.shape[0]))
+    st = S.solve(_dev(f), x, tol=1e-10)
+    xs = _host(x)
+    assert st["converged"]
+    assert st["iterations"] <= ref.iterations + 2
+    assert np.linalg.norm(f - A @ xs) <= residual_bound(A, f, xs)
+    assert st["r_true"] <= 1e-10 * st["r0"]
+    S.close()
