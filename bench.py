@@ -310,6 +310,84 @@ def _extra_workload(name, args):
     return out
 
 
+def _se_step_roofline(S, word, reps=20):
+    """One top-level smoothing step of a continuous handle (residual apply, patch
+    solves, overlap sum) against max(bytes / HBM peak, flops / FP64 peak): flops of
+    the element-local apply 2 D N_P^(D+1) and of the patch solves 4 D n^(D+1)
+    (n = N_P + 2 N_O) per element, bytes 3 words per unknown."""
+    import torch
+    L = S.num_levels - 1
+    P, n_o, n = S.level_info(L)
+    dim = S.grid.dim
+    ne = S.grid.n_elem
+    u = torch.rand(n, dtype=torch.float64, device="cuda")
+    f = torch.rand(n, dtype=torch.float64, device="cuda")
+    S.smooth(L, u, f, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        S.smooth(L, u, f, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    npt = P + 1 + 2 * n_o
+    flops = ne * (2.0 * dim * (P + 1) ** (dim + 1) + 4.0 * dim * npt ** (dim + 1))
+    byts = 3.0 * word * n
+    t_roof = max(byts / (HBM_PEAK_GBPS * 1e9), flops / (FP64_VALU_PEAK_TFLOPS * 1e12)) * 1e3
+    return {"ms": ms, "roof_ms": t_roof, "frac": t_roof / ms, "flops": flops, "alg_bytes": byts}
+
+
+def _se_entry(args):
+    """The continuous spectral-element counterpart of EA_l (Sec. 4.3) on the 16^3 P = 8
+    grid (FP64 and mixed) against DG EA_l (FP64) on the same grid, and the 2D
+    workload of Fig. 6 ((256/P)^2 periodic elements, P = 16) in both discretisations."""
+    import torch
+    import synth
+    from paper_1603_02524_amd import dgmg
+    out = {}
+    for key, ws in (("se_3d", (synth.se_poisson3d_p8(), synth.with_method(synth.c2_poisson3d_p8(), smoother="EA"))),
+                    ("se_fig6_2d_p16", (synth.paper_fig6_2d(16, disc="se"), synth.paper_fig6_2d(16, disc="dg")))):
+        ent = {}
+        secs = {}
+        for w, label in zip(ws, ("se", "dg_ea")):
+            n = w.n_dof
+            rhs_np = synth.rhs_uniform(w.seed if w.seed is not None else 0, n)
+            if all(w.grid.periodic):
+                rhs_np = rhs_np - rhs_np.mean()
+            rhs = torch.tensor(rhs_np, dtype=torch.float64, device="cuda")
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            precs = ("fp64", "mixed") if label == "se" and key == "se_3d" else ("fp64",)
+            for prec in precs:
+                _log(f"{key}: {label} {prec}")
+                S = dgmg.Solver(w.grid, synth.with_method(w, precision=prec).method, max_iter=200)
+                if not args.no_autotune:
+                    S.autotune()
+                if label == "se" and prec == "fp64":
+                    S.kernel_timing(True)
+                sec, e = _solve_entry(S, rhs, x, w.tol, args.warmup, max(2, args.steps // 2))
+                e.update({"workload": w.name, "n_dof": n, "value": n / sec})
+                if label == "se" and prec == "fp64":
+                    kt = S.kernel_time()
+                    S.kernel_timing(False)
+                    k_ms = kt["ms"] / max(kt["launches"], 1)
+                    e["patch_solve"] = {"avg_ms": k_ms, "launches": kt["launches"],
+                                        "achieved_TFLOPs": kt["flops"] / max(kt["launches"], 1) / (k_ms * 1e-3) / 1e12,
+                                        "frac_fp64_peak": kt["flops"] / max(kt["launches"], 1) / (k_ms * 1e-3) / 1e12
+                                        / FP64_VALU_PEAK_TFLOPS}
+                    e["smoothing_step"] = _se_step_roofline(S, 8)
+                ent[f"{label}_{prec}"] = e
+                secs[f"{label}_{prec}"] = sec
+                S.close()
+        ent["se_time_vs_dg_ea_fp64"] = secs["se_fp64"] / secs["dg_ea_fp64"]
+        ent["se_time_per_dof_vs_dg_ea_fp64"] = (secs["se_fp64"] / ent["se_fp64"]["n_dof"]) / (
+            secs["dg_ea_fp64"] / ent["dg_ea_fp64"]["n_dof"])
+        if "se_mixed" in secs:
+            ent["se_mixed_time_vs_se_fp64"] = secs["se_mixed"] / secs["se_fp64"]
+        out[key] = ent
+    return out
+
+
 def _batched_entry(args, small=False):
     """64 grids in one batched MGCG (FP32 V-cycle in FP64 PCG; work-list launches
     shared by the grids' smaller levels) against the same grids solved one after
@@ -443,6 +521,7 @@ def main():
         out["c4"] = _batched_entry(args)
         _log("c4: small batched grids")
         out["c4_small"] = _batched_entry(args, small=True)
+        out["spectral_element"] = _se_entry(args)
 
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle on a bounded sample")

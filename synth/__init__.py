@@ -17,6 +17,8 @@ from .workloads import (  # noqa: F401
     c4_batched,
     c5_poisson3d_p32,
     paper_periodic_2d,
+    paper_fig6_2d,
+    se_poisson3d_p8,
     rhs_uniform,
     guess_uniform01,
     with_method,

@@ -208,5 +208,20 @@ def paper_periodic_2d(P: int, n: int = 16, ar: int = 1, smoother: str = "EA",
     return Workload(f"periodic2d_{n}x{n}_ar{ar}_p{P}_{smoother}", g, m, 0, "manufactured")
 
 
+def se_poisson3d_p8(n: int = 16) -> Workload:
+    """The continuous spectral-element counterpart of EA_l on the 3D grid of
+    poisson3d_16^3_p8: [0,1]^3, n^3 elements, P = 8, Dirichlet, U[-1,1] RHS, FP64."""
+    g = uniform_grid(3, n, 1.0, False)
+    m = Method(P=8, smoother="EA", overlap="level", disc="se")
+    return Workload(f"se_poisson3d_{n}^3_p8_ea_fp64", g, m, 6, "uniform")
+
+
+def paper_fig6_2d(P: int, disc: str = "dg") -> Workload:
+    """The workload of Fig. 6: (256/P)^2 square elements of order P on the paper's
+    periodic domain (0, 2)^2, EA_l (DG or its continuous counterpart)."""
+    w = paper_periodic_2d(P, n=256 // P, smoother="EA")
+    return Workload(f"fig6_{disc}_{256 // P}x{256 // P}_p{P}_ea", w.grid, replace(w.method, disc=disc), 7, "uniform")
+
+
 def with_method(w: Workload, **kw) -> Workload:
     return replace(w, method=replace(w.method, **kw))
