@@ -35,13 +35,10 @@ __device__ __forceinline__ int se_stored(int g, int P, int N, int periodic) {
   return (g >= 1 && g <= G - 1) ? g - 1 : -1;
 }
 
+// Elements per block of the element kernels: about 256 lines of one direction.
 template <int NP, int DIM>
 constexpr int se_epb() {
-  return imax(1, 256 / ipow(NP, DIM));
-}
-template <int DIM, int NP>
-inline int se_elem_blocks(int n_elem) {
-  return (n_elem + se_epb<NP, DIM>() - 1) / se_epb<NP, DIM>();
+  return imax(1, 256 / ipow(NP, DIM - 1));
 }
 
 // Lattice strides of the directions of level L.
@@ -72,22 +69,29 @@ __device__ __forceinline__ void se_elem_offsets(const LevelDev<T>& L, int e0, in
 }
 
 // w_e = A_e x_e for every element (element-major output, NP^DIM per element):
-// A_e = sum_d (x)_{d' != d} (dx_{d'}/2) diag(rho) (x) (2/dx_d) L^s.
+// A_e = sum_d (x)_{d' != d} (dx_{d'}/2) diag(rho) (x) (2/dx_d) L^s.  The block's
+// elements are staged in LDS; then one pass per direction with one thread per
+// line of that direction: the line's NP values in registers, the rows of L^s
+// as uniform (scalar) operands, the line's factor (2/dx_d) prod (dx_d'/2) rho
+// applied once per output; the passes accumulate in a second LDS tile in
+// direction order.
 template <class T, int DIM, int NP>
-__global__ void __launch_bounds__(256) se_elem_kernel(LevelDev<T> L, const T* __restrict__ x, T* __restrict__ w,
-                                                      int nblk) {
-  constexpr int NE = ipow(NP, DIM), EPB = se_epb<NP, DIM>();
-  constexpr int NZ = DIM == 3 ? NP : 1;
-  __shared__ T xs[EPB][NE];
-  __shared__ T sL[NP * NP];
+__global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* __restrict__ x, T* __restrict__ w,
+                                                       int nblk, int epb) {
+  constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = se_epb<NP, DIM>();
+  __shared__ T xs[EPB * NE];
+  __shared__ T acc[EPB * NE];
   __shared__ T srho[NP];
   __shared__ int64_t off[EPB][3][NP];
   __shared__ T two[EPB][3], half[EPB][3];
+  constexpr bool SLS = NP * sizeof(T) <= 72;  // rows fit the scalar registers
+  __shared__ T sLs[SLS ? 1 : NP * NP];
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
-  const int e0 = blk * EPB, ne = imin(EPB, L.n_elem - e0);
+  const int e0 = blk * epb, ne = imin(imin(epb, EPB), L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int q = tid; q < NP * NP; q += nth) sL[q] = L.Ls[q];
+  if constexpr (!SLS)
+    for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
   for (int q = tid; q < NP; q += nth) srho[q] = L.rho[q];
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   for (int q = tid; q < ne * 3; q += nth) {
@@ -103,33 +107,67 @@ __global__ void __launch_bounds__(256) se_elem_kernel(LevelDev<T> L, const T* __
   }
   se_elem_offsets<T, DIM, NP, EPB>(L, e0, ne, off);
   __syncthreads();
-  for (int q = tid; q < ne * NE; q += nth) {
-    const int el = q / NE, loc = q - el * NE;
-    const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
-    const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
-    const bool ok = (a | b | c) >= 0;
-    const T v = x[ok ? a + b + c : 0];
-    xs[el][loc] = ok ? v : T(0);
+  // gather: GU loads of a thread in flight before their LDS stores
+  constexpr int GU = 8;
+  for (int q0 = tid; q0 < ne * NE; q0 += GU * nth) {
+    T v[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int q = q0 + u * nth;
+      const int qq = q < ne * NE ? q : 0;
+      const int el = qq / NE, loc = qq - el * NE;
+      const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
+      const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
+      const bool ok = q < ne * NE && (a | b | c) >= 0;
+      T t = T(0);
+      if (ok) t = x[a + b + c];
+      v[u] = t;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+      if (q0 + u * nth < ne * NE) xs[q0 + u * nth] = v[u];
   }
   __syncthreads();
-  for (int q = tid; q < ne * NE; q += nth) {
-    const int el = q / NE, loc = q - el * NE;
-    const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
-    const T* t = xs[el];
-    T sx = T(0), sy = T(0), sz = T(0);
-#pragma unroll 4
-    for (int a = 0; a < NP; ++a) {
-      sx += sL[i * NP + a] * t[(k * NP + j) * NP + a];
-      sy += sL[j * NP + a] * t[(k * NP + a) * NP + i];
-      if (DIM == 3) sz += sL[k * NP + a] * t[(a * NP + j) * NP + i];
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Ls = (CT*)L.Ls;
+#pragma unroll 1
+  for (int d = 0; d < DIM; ++d) {
+    // line (el, o1, o2): o1, o2 the other directions' indices in increasing direction order
+    const int st = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
+    for (int q = tid; q < ne * NLN; q += nth) {
+      const int el = q / NLN, ln = q - el * NLN;
+      const int o1 = ln % NP, o2 = DIM == 3 ? ln / NP : 0;
+      int base;
+      T fac = two[el][d];
+      if (d == 0) {
+        base = (o2 * NP + o1) * NP;
+        fac *= half[el][1] * srho[o1];
+        if (DIM == 3) fac *= half[el][2] * srho[o2];
+      } else if (d == 1) {
+        base = o2 * NP * NP + o1;
+        fac *= half[el][0] * srho[o1];
+        if (DIM == 3) fac *= half[el][2] * srho[o2];
+      } else {
+        base = o2 * NP + o1;
+        fac *= half[el][0] * srho[o1] * half[el][1] * srho[o2];
+      }
+      const T* src = xs + el * NE + base;
+      T* dst = acc + el * NE + base;
+      T v[NP];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) v[a] = src[a * st];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) s += (SLS ? (T)Ls[i * NP + a] : sLs[i * NP + a]) * v[a];
+        s *= fac;
+        dst[i * st] = d == 0 ? s : dst[i * st] + s;
+      }
     }
-    const T mx = half[el][0] * srho[i], my = half[el][1] * srho[j];
-    const T mz = DIM == 3 ? half[el][2] * srho[k] : T(1);
-    T v = two[el][0] * sx * my * mz + mx * two[el][1] * sy * mz;
-    if (DIM == 3) v += mx * my * two[el][2] * sz;
-    w[(int64_t)(e0 + el) * NE + loc] = v;
+    __syncthreads();
   }
-  (void)NZ;
+  for (int q = tid; q < ne * NE; q += nth) w[(int64_t)e0 * NE + q] = acc[q];
 }
 
 // Lattice node q of level L: per direction the (element, local node) pairs of
@@ -162,47 +200,67 @@ __device__ __forceinline__ void se_node_owners(const LevelDev<T>& L, int64_t q, 
   }
 }
 
-// y = sum of the element copies (MODE 0), y = f - sum (MODE 1).
+// y = sum of the element copies (MODE 0), y = f - sum (MODE 1).  All 2^DIM
+// candidate slots are loaded at once (empty ones masked off) and added in the
+// fixed order direction 3, 2, 1.
 template <class T, int DIM, int NP>
 __global__ void __launch_bounds__(256) se_dss_kernel(LevelDev<T> L, const T* __restrict__ w,
                                                      const T* __restrict__ f, T* __restrict__ y, int mode) {
   if (inactive(L.active)) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.n_dof) return;
-  constexpr int NE = ipow(NP, DIM);
+  constexpr int NE = ipow(NP, DIM), CZ = DIM == 3 ? 2 : 1;
   int cnt[3], em[3][2], lo[3][2];
   se_node_owners<T, DIM>(L, q, cnt, em, lo);
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
-  T s = T(0);
-  for (int c = 0; c < cnt[2]; ++c)
-    for (int b = 0; b < cnt[1]; ++b)
-      for (int a = 0; a < cnt[0]; ++a) {
-        const int64_t e = em[0][a] + (int64_t)N1 * (em[1][b] + (int64_t)N2 * em[2][c]);
-        s += w[e * NE + (lo[2][c] * NP + lo[1][b]) * NP + lo[0][a]];
+  T v[CZ][2][2];
+#pragma unroll
+  for (int c = 0; c < CZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const bool ok = a < cnt[0] && b < cnt[1] && c < cnt[2];
+        const int64_t e = em[0][ok ? a : 0] + (int64_t)N1 * (em[1][ok ? b : 0] + (int64_t)N2 * em[2][ok ? c : 0]);
+        const int64_t idx = e * NE + (lo[2][ok ? c : 0] * NP + lo[1][ok ? b : 0]) * NP + lo[0][ok ? a : 0];
+        T t = T(0);
+        if (ok) t = w[idx];
+        v[c][b][a] = t;
       }
+  T s = T(0);
+#pragma unroll
+  for (int c = 0; c < CZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        if (a < cnt[0] && b < cnt[1] && c < cnt[2]) s += v[c][b][a];
   y[q] = mode == 1 ? f[q] - s : s;
 }
 
 // u (+)= sum over the element-centred patches covering each lattice node of
 // their weighted corrections (buf: one NA^DIM tile per patch, patch index
 // m1 + N1 (m2 + N2 m3), tile position t1 + NA (t2 + NA t3), patch m's tile
-// starting at lattice position m P - N_O).  Sum order: direction 3, 2, 1
-// candidates, each in increasing patch index.
-template <class T, int DIM>
+// starting at lattice position m P - N_O).  MAXC: most patches covering a node
+// per direction (2 when 2 N_O < P, else 3).  All candidate slots are loaded at
+// once (empty ones masked off); sum order direction 3, 2, 1 candidates, each
+// in increasing patch index.
+template <class T, int DIM, int MAXC>
 __global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, const T* __restrict__ buf,
                                                          T* __restrict__ u, int assign) {
   if (inactive(L.active)) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.n_dof) return;
+  constexpr int CZ = DIM == 3 ? MAXC : 1;
   const int P = L.P, NO = L.NO;
-  int cnt[3], pm[3][3], tp[3][3];
+  int cnt[3], pm[3][MAXC], tp[3][MAXC];
   int64_t rest = q;
   for (int d = 0; d < 3; ++d) {
     cnt[d] = 0;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k) pm[d][k] = tp[d][k] = 0;
     if (d >= DIM) {
       cnt[d] = 1;
-      pm[d][0] = 0;
-      tp[d][0] = 0;
       continue;
     }
     const DirDev<T>& dd = L.dir[d];
@@ -210,25 +268,41 @@ __global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, 
     rest /= dd.nl;
     const int g = dd.periodic ? s : s + 1;
     const int m0 = g / P;
+#pragma unroll
     for (int k = -2; k <= 1; ++k) {
       const int m = m0 + k;
       const int t = g - (m * P - NO);
-      if (t < 0 || t >= NA || cnt[d] >= 3) continue;
-      if (!dd.periodic && (m < 0 || m >= dd.N)) continue;
-      pm[d][cnt[d]] = ((m % dd.N) + dd.N) % dd.N;
-      tp[d][cnt[d]] = t;
-      ++cnt[d];
+      const bool in = t >= 0 && t < NA && cnt[d] < MAXC && (dd.periodic || (m >= 0 && m < dd.N));
+      if (in) {
+        pm[d][cnt[d]] = ((m % dd.N) + dd.N) % dd.N;
+        tp[d][cnt[d]] = t;
+        ++cnt[d];
+      }
     }
   }
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
   const int64_t TS = DIM == 3 ? (int64_t)NA * NA * NA : (int64_t)NA * NA;
-  T s = T(0);
-  for (int c = 0; c < cnt[2]; ++c)
-    for (int b = 0; b < cnt[1]; ++b)
-      for (int a = 0; a < cnt[0]; ++a) {
+  T v[CZ][MAXC][MAXC];
+#pragma unroll
+  for (int c = 0; c < CZ; ++c)
+#pragma unroll
+    for (int b = 0; b < MAXC; ++b)
+#pragma unroll
+      for (int a = 0; a < MAXC; ++a) {
+        const bool ok = a < cnt[0] && b < cnt[1] && c < cnt[2];
         const int64_t pid = pm[0][a] + (int64_t)N1 * (pm[1][b] + (int64_t)N2 * pm[2][c]);
-        s += buf[pid * TS + ((int64_t)tp[2][c] * NA + tp[1][b]) * NA + tp[0][a]];
+        T t = T(0);
+        if (ok) t = buf[pid * TS + ((int64_t)tp[2][c] * NA + tp[1][b]) * NA + tp[0][a]];
+        v[c][b][a] = t;
       }
+  T s = T(0);
+#pragma unroll
+  for (int c = 0; c < CZ; ++c)
+#pragma unroll
+    for (int b = 0; b < MAXC; ++b)
+#pragma unroll
+      for (int a = 0; a < MAXC; ++a)
+        if (a < cnt[0] && b < cnt[1] && c < cnt[2]) s += v[c][b][a];
   u[q] = assign ? s : u[q] + s;
 }
 
@@ -351,8 +425,13 @@ int se_apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y
     return -4;  // element tiles beyond LDS
   } else {
     if (mode != 0 && mode != 1) return -4;
-    const int nb = se_elem_blocks<DIM, NP>(L.n_elem);
-    hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP>), dim3(xcd_grid(nb)), dim3(256), 0, s, L, x, ebuf, nb);
+    // elements per block: up to se_epb, fewer on small levels so that the
+    // launch still has about 512 blocks
+    constexpr int EPB = se_epb<NP, DIM>(), NLN = ipow(NP, DIM - 1);
+    const int epb = imax(1, imin(EPB, L.n_elem / 512));
+    const int nb = (L.n_elem + epb - 1) / epb;
+    const int th = imin(1024, round64(epb * NLN));
+    hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP>), dim3(xcd_grid(nb)), dim3(th), 0, s, L, x, ebuf, nb, epb);
     hipLaunchKernelGGL((se_dss_kernel<T, DIM, NP>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L,
                        (const T*)ebuf, f, y, mode);
     return 0;
@@ -361,8 +440,12 @@ int se_apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y
 
 template <class T, int DIM>
 int se_combine_launch(const LevelDev<T>& L, int NA, const T* buf, T* u, bool assign, hipStream_t s) {
-  hipLaunchKernelGGL((se_combine_kernel<T, DIM>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L, NA, buf, u,
-                     assign ? 1 : 0);
+  if (2 * L.NO < L.P)
+    hipLaunchKernelGGL((se_combine_kernel<T, DIM, 2>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L, NA, buf, u,
+                       assign ? 1 : 0);
+  else
+    hipLaunchKernelGGL((se_combine_kernel<T, DIM, 3>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L, NA, buf, u,
+                       assign ? 1 : 0);
   return 0;
 }
 
