@@ -453,6 +453,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB MiB (PMC calibration) and exit")
+    ap.add_argument("--se-only", action="store_true",
+                    help="only the continuous spectral-element entry (for profiling), printed as its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the solver "
@@ -461,6 +463,9 @@ def main():
 
     if args.copy_calibration:
         _copy_calibration(args.copy_calibration)
+        return
+    if args.se_only:
+        print(json.dumps({"spectral_element": _se_entry(args)}), flush=True)
         return
 
     import torch

@@ -75,7 +75,9 @@ __device__ __forceinline__ void se_elem_offsets(const LevelDev<T>& L, int e0, in
 // as uniform (scalar) operands, the line's factor (2/dx_d) prod (dx_d'/2) rho
 // applied once per output; the passes accumulate in a second LDS tile in
 // direction order.
-template <class T, int DIM, int NP>
+// PN (small levels, few lines per block): one thread per line and output
+// instead of per line, so that short launches still have enough parallel work.
+template <class T, int DIM, int NP, bool PN>
 __global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* __restrict__ x, T* __restrict__ w,
                                                        int nblk, int epb) {
   constexpr int NE = ipow(NP, DIM), NLN = ipow(NP, DIM - 1), EPB = se_epb<NP, DIM>();
@@ -134,7 +136,9 @@ __global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* _
   for (int d = 0; d < DIM; ++d) {
     // line (el, o1, o2): o1, o2 the other directions' indices in increasing direction order
     const int st = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
-    for (int q = tid; q < ne * NLN; q += nth) {
+    constexpr int CH = PN ? NP : 1;  // work items per line
+    for (int qq = tid; qq < ne * NLN * CH; qq += nth) {
+      const int q = PN ? qq / NP : qq;
       const int el = q / NLN, ln = q - el * NLN;
       const int o1 = ln % NP, o2 = DIM == 3 ? ln / NP : 0;
       int base;
@@ -153,16 +157,26 @@ __global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* _
       }
       const T* src = xs + el * NE + base;
       T* dst = acc + el * NE + base;
-      T v[NP];
-#pragma unroll
-      for (int a = 0; a < NP; ++a) v[a] = src[a * st];
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
+      if constexpr (PN) {
+        const int i = qq - q * NP;
+        const T* lrow = SLS ? nullptr : sLs + i * NP;
         T s = T(0);
 #pragma unroll
-        for (int a = 0; a < NP; ++a) s += (SLS ? (T)Ls[i * NP + a] : sLs[i * NP + a]) * v[a];
+        for (int a = 0; a < NP; ++a) s += (SLS ? L.Ls[i * NP + a] : lrow[a]) * src[a * st];
         s *= fac;
         dst[i * st] = d == 0 ? s : dst[i * st] + s;
+      } else {
+        T v[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) v[a] = src[a * st];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          T s = T(0);
+#pragma unroll
+          for (int a = 0; a < NP; ++a) s += (SLS ? (T)Ls[i * NP + a] : sLs[i * NP + a]) * v[a];
+          s *= fac;
+          dst[i * st] = d == 0 ? s : dst[i * st] + s;
+        }
       }
     }
     __syncthreads();
@@ -430,8 +444,14 @@ int se_apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y
     constexpr int EPB = se_epb<NP, DIM>(), NLN = ipow(NP, DIM - 1);
     const int epb = imax(1, imin(EPB, L.n_elem / 512));
     const int nb = (L.n_elem + epb - 1) / epb;
-    const int th = imin(1024, round64(epb * NLN));
-    hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP>), dim3(xcd_grid(nb)), dim3(th), 0, s, L, x, ebuf, nb, epb);
+    if ((int64_t)nb * epb * NLN < 128 * 1024) {  // fewer than ~128k lines: a thread per line and output
+      const int th = imin(1024, round64(epb * NLN * NP));
+      hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP, true>), dim3(xcd_grid(nb)), dim3(th), 0, s, L, x, ebuf, nb, epb);
+    } else {
+      const int th = imin(1024, round64(epb * NLN));
+      hipLaunchKernelGGL((se_elem_kernel<T, DIM, NP, false>), dim3(xcd_grid(nb)), dim3(th), 0, s, L, x, ebuf, nb,
+                         epb);
+    }
     hipLaunchKernelGGL((se_dss_kernel<T, DIM, NP>), dim3(se_node_blocks(L.n_dof)), dim3(256), 0, s, L,
                        (const T*)ebuf, f, y, mode);
     return 0;
