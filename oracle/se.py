@@ -209,6 +209,26 @@ def assemble_kron(grid, P: int) -> sp.csr_matrix:
     return A.tocsr()
 
 
+def apply_kron(grid, P: int, u: np.ndarray, ops=None) -> np.ndarray:
+    """A u in the Kronecker form, axis by axis with the assembled 1D matrices
+    (the same operator as ``assemble_kron``; for grids too large to assemble)."""
+    dim = grid.dim
+    if ops is None:
+        ops = [assemble_1d(P, grid.dx[d], grid.periodic[d]) for d in range(dim)]
+    U = np.asarray(u, dtype=np.float64).reshape(lattice_shape(grid, P))
+    y = np.zeros_like(U)
+    for d in range(dim):
+        ax = dim - 1 - d
+        t = np.moveaxis(np.moveaxis(U, ax, -1) @ ops[d][1].T, -1, ax)
+        for dd in range(dim):
+            if dd != d:
+                sh = [1] * dim
+                sh[dim - 1 - dd] = -1
+                t = t * ops[dd][0].reshape(sh)
+        y += t
+    return y.reshape(-1)
+
+
 def apply(grid, P: int, u: np.ndarray) -> np.ndarray:
     """A u matrix-free: per element gather, local operator, scatter-add."""
     dim = grid.dim
@@ -444,7 +464,7 @@ class SEHierarchy:
         lev = self.levels[l]
         if lev.A is not None:
             return lev.A @ u
-        return apply(self.grid, lev.P, u)
+        return apply_kron(self.grid, lev.P, u, ops=lev.smoother.ops1 if lev.smoother is not None else None)
 
     def prolong(self, l: int, uc: np.ndarray) -> np.ndarray:
         return self._I[l] @ uc

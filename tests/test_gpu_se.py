@@ -216,3 +216,72 @@ def test_mixed_precision_solve(cid):
     assert np.linalg.norm(f - A @ xs) <= residual_bound(A, f, xs)
     assert st["r_true"] <= 1e-10 * st["r0"]
     S.close()
+
+
+def _kron_residual_se(grid, P, f, x, tol=1e-10):
+    """(||f - A x||, bound) with the oracle's matrix-free Kronecker operator; bound =
+    tol ||f|| + 2 gamma_m || |f| + |A| |x| ||, m = D (2P + 1) terms in a row."""
+    ops = [se.assemble_1d(P, grid.dx[d], grid.periodic[d]) for d in range(grid.dim)]
+    r = f - se.apply_kron(grid, P, x, ops=ops)
+    aops = [(M, np.abs(L)) for M, L in ops]
+    ax = se.apply_kron(grid, P, np.abs(x), ops=aops)
+    m = grid.dim * (2 * P + 1)
+    u = np.finfo(np.float64).eps / 2
+    gam = m * u / (1 - m * u)
+    return np.linalg.norm(r), tol * np.linalg.norm(f) + 2 * gam * np.linalg.norm(np.abs(f) + ax)
+
+
+def test_fullsize_fp64_solve_matches_oracle_mgcg():
+    """The continuous 16^3 P = 8 workload (2,048,383 unknowns): the library's MGCG
+    against the oracle's full solve recorded by tests/golden/make_se_reference.py —
+    the same iteration count, the residual history within 1e-6, the final iterate
+    at 4096 sampled positions and its 2-norm within 1e-10, and the true residual
+    (oracle operator) within 1e-10 ||f|| up to its evaluation rounding."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "se_oracle_mgcg.json")
+    with open(path) as fh:
+        ref = json.load(fh)
+    w = synth.se_poisson3d_p8()
+    g, m = w.grid, w.method
+    n = w.n_dof
+    assert ref["n_dof"] == n and ref["workload"] == w.name
+    print("[case se 16^3 p8 fp64 full size]", flush=True)
+    S = D.Solver(g, m, max_iter=200)
+    try:
+        f_np = synth.rhs_uniform(w.seed, n)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st = S.solve(_dev(f_np), x, tol=ref["tol"])
+        k = st["iterations"]
+        print(f"  se 16^3 fp64: {k} iterations (oracle {ref['iterations']})", flush=True)
+        assert st["converged"] and k == ref["iterations"]
+        assert np.allclose(st["history"][: k + 1], ref["history"], rtol=1e-6, atol=0)
+        it = ref["iterates"][str(k)]
+        idx = np.asarray(ref["sample_index"])
+        xs = _host(x)
+        xr = np.asarray(it["x"])
+        err = np.abs(xs[idx] - xr).max() / np.abs(xr).max()
+        nerr = abs(np.linalg.norm(xs) - it["norm"]) / it["norm"]
+        print(f"  se 16^3 fp64 iterate: sampled rel err {err:.2e}, norm rel err {nerr:.2e}", flush=True)
+        assert err <= 1e-10 and nerr <= 1e-10
+        rn, bound = _kron_residual_se(g, m.P, f_np, xs)
+        assert rn <= bound, (rn, bound)
+    finally:
+        S.close()
+
+
+def test_fullsize_mixed_solve_reaches_the_true_residual():
+    w = synth.with_method(synth.se_poisson3d_p8(), precision="mixed")
+    g, m = w.grid, w.method
+    n = w.n_dof
+    print("[case se 16^3 p8 mixed full size]", flush=True)
+    S = D.Solver(g, m, max_iter=200)
+    try:
+        f_np = synth.rhs_uniform(w.seed, n)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st = S.solve(_dev(f_np), x, tol=w.tol)
+        assert st["converged"] and st["r_true"] <= w.tol * st["r0"]
+        rn, bound = _kron_residual_se(g, m.P, f_np, _host(x))
+        assert rn <= bound, (rn, bound)
+    finally:
+        S.close()

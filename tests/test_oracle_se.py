@@ -70,6 +70,7 @@ def test_assembly_matches_kronecker_form(dim, periodic, P):
     assert abs(A - se.assemble_kron(g, P)).max() < 1e-12 * abs(K).max()
     u = np.random.default_rng(1).standard_normal(A.shape[0])
     assert np.allclose(se.apply(g, P, u), A @ u, rtol=0, atol=1e-12 * np.abs(A @ u).max())
+    assert np.allclose(se.apply_kron(g, P, u), A @ u, rtol=0, atol=1e-12 * np.abs(A @ u).max())
     assert abs(A - A.T).max() < 1e-13 * abs(A).max()
 
 
