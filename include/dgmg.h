@@ -117,7 +117,9 @@ typedef struct {
 } dgmg_grid;
 
 typedef struct {
-  int P;             /* top-level order, 1 <= P <= 32 (kernels for P_l in 1,2,3,4,6,8,12,16,32) */
+  int P;             /* top-level order, 1 <= P <= 32: compiled kernels for P_l in 1,2,3,4,6,8,12,16,32,
+                        run-time kernels (same results, slower) for the other orders; 3D takes
+                        P <= 17 or P = 32 (the run-time patch tiles must fit the LDS) */
   int flux;          /* DGMG_FLUX_IP or DGMG_FLUX_LDG */
   double beta[3];    /* LDG parameter per direction (Sec. 2.3); ignored for IP */
   double mu_star;    /* penalty factor mu_star > 0 of mu = mu_0 (1 + mu_star) */

@@ -768,6 +768,19 @@ int k_apply(dgmg_handle* h, int l, int mode, const T* x, const T* f, T* y, doubl
     }
     return check_hip(h, "apply");
   }
+  const bool comp = L.dim == 3 ? Kern<T, 3>::order_compiled(L.NP) : Kern<T, 2>::order_compiled(L.NP);
+  if (!comp && mode == 2) {  // run-time orders: the operator, then the partial sums of x.y
+    int rc = L.dim == 3 ? Kern<T, 3>::apply(L, 0, x, f, y, scratch, part, nb, h->stream)
+                        : Kern<T, 2>::apply(L, 0, x, f, y, scratch, part, nb, h->stream);
+    if (rc) return fail(h, DGMG_EUNSUPPORTED, "no operator kernel for this order");
+    if constexpr (std::is_same<T, double>::value) {
+      hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(VEC_THREADS), 0, h->stream, x, y, L.n_dof, part, h->active);
+      *nb = RED_BLOCKS;
+      return check_hip(h, "apply");
+    } else {
+      return fail(h, DGMG_EINVAL, "mode 2 is FP64 only");
+    }
+  }
   int rc = L.dim == 3 ? Kern<T, 3>::apply(L, mode, x, f, y, scratch, part, nb, h->stream)
                       : Kern<T, 2>::apply(L, mode, x, f, y, scratch, part, nb, h->stream);
   if (rc) return fail(h, DGMG_EUNSUPPORTED, "no operator kernel for this order");
@@ -1295,9 +1308,15 @@ int check_level(dgmg_handle* h, int level, int minl = 0) {
 int validate_setup(const dgmg_grid* g, const dgmg_opts* o, SetupParams& sp) {
   if (!g || !o) return fail(nullptr, DGMG_EINVAL, "null argument");
   if (g->dim != 2 && g->dim != 3) return fail(nullptr, DGMG_EINVAL, "dim must be 2 or 3");
+  if (o->P < 1 || o->P > 32) return fail(nullptr, DGMG_EINVAL, "P must be in 1 .. 32");
+  // compiled kernels for P_l in {1, 2, 3, 4, 6, 8, 12, 16, 32}; other orders run
+  // the run-time kernels, whose 3D tiles fit the LDS up to P = 17
   const int okP[] = {1, 2, 3, 4, 6, 8, 12, 16, 32};
-  if (std::find(std::begin(okP), std::end(okP), o->P) == std::end(okP))
-    return fail(nullptr, DGMG_EUNSUPPORTED, "P must be one of 1, 2, 3, 4, 6, 8, 12, 16, 32");
+  const bool compiled = std::find(std::begin(okP), std::end(okP), o->P) != std::end(okP);
+  if (g->dim == 3 && o->P > 17 && o->P != 32)
+    return fail(nullptr, DGMG_EUNSUPPORTED, "3D orders 18 .. 31 are not built (their patch tiles exceed the LDS)");
+  if (o->disc == DGMG_DISC_SE && !compiled)
+    return fail(nullptr, DGMG_EUNSUPPORTED, "the continuous counterpart needs P in 1, 2, 3, 4, 6, 8, 12, 16, 32");
   if (!(o->mu_star > 0) || !std::isfinite(o->mu_star)) return fail(nullptr, DGMG_EINVAL, "mu_star must be > 0");
   if (o->flux != DGMG_FLUX_IP && o->flux != DGMG_FLUX_LDG) return fail(nullptr, DGMG_EINVAL, "bad flux");
   if (o->smoother < DGMG_SMOOTHER_EA || o->smoother > DGMG_SMOOTHER_FM) return fail(nullptr, DGMG_EINVAL, "bad smoother");
@@ -2011,8 +2030,12 @@ bool batch_plannable(const dgmg_batch* b) {
     if (h->opts.precision != h0->opts.precision || h->opts.ns_pre != h0->opts.ns_pre ||
         h->opts.ns_post != h0->opts.ns_post || h->opts.vcycle != h0->opts.vcycle)
       return false;
-    for (const LevelHost& lv : h->lv)
+    for (const LevelHost& lv : h->lv) {
       if (lv.dim == 3 && lv.NP == BIG_NP) return false;
+      // run-time orders have no work-list launches
+      if (!(lv.dim == 3 ? Kern<double, 3>::order_compiled(lv.NP) : Kern<double, 2>::order_compiled(lv.NP)))
+        return false;
+    }
   }
   return true;
 }

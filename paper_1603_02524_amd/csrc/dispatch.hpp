@@ -5,6 +5,7 @@
 #include "kernels.hpp"
 #include "kernels_big.hpp"
 #include "kernels_se.hpp"
+#include "kernels_gen.hpp"
 
 namespace dgmg {
 
@@ -37,7 +38,19 @@ int Kern<T, DIM>::apply(const LevelDev<T>& L, int mode, const T* x, const T* f, 
       return apply_launch<T, DIM, NP>(L, mode, x, f, y, part, nblk, s);
     DGMG_NP_LIST(DGMG_CASE)
 #undef DGMG_CASE
-    default: return -4;
+    default:  // orders without compiled kernels: the run-time form (modes 0 and 1)
+      return gen_apply_launch<T>(L, mode, x, f, y, s);
+  }
+}
+
+template <class T, int DIM>
+bool Kern<T, DIM>::order_compiled(int NP) {
+  switch (NP) {
+#define DGMG_CASE(N) \
+  case N: return true;
+    DGMG_NP_LIST(DGMG_CASE)
+#undef DGMG_CASE
+    default: return false;
   }
 }
 
@@ -50,7 +63,7 @@ bool Kern<T, DIM>::fdm_supported(int NA, int NL) {
     DGMG_FDM_LIST_2D(DGMG_CASE)
   }
 #undef DGMG_CASE
-  return false;
+  return gen_fdm_fits<T>(DIM, NA, NL);  // the run-time tile form
 }
 
 template <class T, int DIM>
@@ -62,7 +75,7 @@ bool Kern<T, DIM>::fdm_in_lds(int NA, int NL) {
     DGMG_FDM_LIST_2D(DGMG_CASE)
   }
 #undef DGMG_CASE
-  return false;
+  return gen_fdm_fits<T>(DIM, NA, NL);
 }
 
 template <class T, int DIM>
@@ -85,7 +98,7 @@ int Kern<T, DIM>::fdm(const LevelDev<T>& L, int nd, int NA, int NL, const T* r, 
     DGMG_FDM_LIST_2D(DGMG_CASE)
 #undef DGMG_CASE
   }
-  return -4;
+  return gen_fdm_launch<T>(L, nd, NA, NL, r, out, npx, npy, npz, lat, s);  // run-time tile
 }
 
 template <class T, int DIM>
@@ -202,7 +215,7 @@ int Kern<T, DIM>::combine(const LevelDev<T>& L, int nd, int NA, int NL, const T*
   case NP: return combine_launch_t<T, DIM, NP>(L, nd, NA, NL, buf, u, npx, npy, npz, assign, s);
     DGMG_NP_LIST(DGMG_CASE)
 #undef DGMG_CASE
-    default: return -4;
+    default: return gen_combine_launch<T>(L, nd, NA, NL, buf, u, npx, npy, assign, s);
   }
 }
 
@@ -219,7 +232,7 @@ int Kern<T, DIM>::transfer(const LevelDev<T>& Lf, bool restrict_, const T* in, T
   }
   DGMG_XFER_LIST(DGMG_CASE)
 #undef DGMG_CASE
-  return -4;
+  return gen_transfer_launch<T>(Lf, restrict_, in, out, s);  // run-time orders
 }
 
 template <class T, int DIM>

@@ -1584,6 +1584,8 @@ struct Kern {
   static int transfer_batch(int NPF, int NPC, bool restrict_, const BatchList<XferArgs<T>>& bl, int ntot,
                             hipStream_t s);
   static bool fdm_supported(int NA, int NL);
+  // the order has compiled kernels (others run the run-time forms of kernels_gen.hpp)
+  static bool order_compiled(int NP);
   // the tile's solve runs in LDS (not the large-tile stages through global memory)
   static bool fdm_in_lds(int NA, int NL);
   // assign: u = the overlap sum (u is zero on entry) instead of u += it

@@ -48,6 +48,16 @@ CASES = [
     # P = 32: 3D elements and patch tiles beyond LDS (two-stage transfers, three-stage patch solves)
     ("3d_dir_ip_p32_fa", dict(dim=3, n=(2, 1, 2), seed=11), dict(P=32, smoother="FA")),
     ("3d_dir_ip_p32_ea", dict(dim=3, n=(1, 2, 2), seed=12), dict(P=32, smoother="EA")),
+    # orders without compiled kernels (run-time order and tile forms), alone and
+    # next to compiled levels of the same series
+    ("2d_dir_ip_p5_ea", dict(dim=2, n=(4, 3), seed=41), dict(P=5, smoother="EA")),
+    ("3d_dir_ip_p7_fa", dict(dim=3, n=(2, 3, 2), seed=42), dict(P=7, smoother="FA")),
+    ("3d_per_ldg_p10_fa", dict(dim=3, n=(3, 3, 3), periodic=True, seed=43),
+     dict(P=10, smoother="FA", flux="ldg", beta=(0.5, 0.5, 0.5))),
+    ("2d_per_ip_p24_ea", dict(dim=2, n=(3, 3), periodic=True, seed=44), dict(P=24, smoother="EA")),
+    ("3d_dir_ip_p17_fa", dict(dim=3, n=(2, 1, 2), seed=45), dict(P=17, smoother="FA")),
+    ("3d_mixed_ip_p9_ea0", dict(dim=3, n=(2, 3, 2), periodic=(False, True, False), seed=46),
+     dict(P=9, smoother="EA", overlap="zero")),
 ]
 
 

@@ -45,7 +45,7 @@ def test_defaults():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(P=5), dict(P=0), dict(mu_star=0.0), dict(mu_star=-1.0), dict(smoother="XX"),
+    dict(P=33), dict(P=0), dict(P=20), dict(mu_star=0.0), dict(mu_star=-1.0), dict(smoother="XX"),
 ])
 def test_setup_rejects_bad_options(bad):
     g = synth.uniform_grid(3, 2, 1.0, False)
@@ -84,7 +84,7 @@ def test_level_series_and_geometry_match_oracle():
     lib = D.load_library()
     rng = np.random.default_rng(0)
     g = synth.Grid(3, tuple(rng.uniform(0.2, 1.0, 3) for _ in range(3)), (False,) * 3)
-    for P in (1, 2, 3, 4, 6, 8, 12, 16):
+    for P in (1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 13, 16, 17):
         for ov in ("level", "level_floor", "zero"):
             m = synth.Method(P=P, smoother="FA", overlap=ov)
             h, keep = D.setup_handle(g, m)

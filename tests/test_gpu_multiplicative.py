@@ -38,6 +38,8 @@ CASES = {
     "3d_mixed_ldg_p4_em0_lex": (dict(dim=3, n=(3, 3, 2), periodic=(True, False, False), seed=67),
                                 dict(P=4, smoother="EM", overlap="zero", flux="ldg", beta=(0.5, 0.5, 0.5),
                                      order="lex")),
+    # a run-time order (P = 5: no compiled kernels) with colour-class patch lattices
+    "3d_dir_ip_p5_fml_colour": (dict(dim=3, n=(3, 2, 3), seed=68), dict(P=5, smoother="FM", order="colour")),
 }
 
 
