@@ -449,6 +449,7 @@ struct dgmg_batch {
     size_t desc_off = 0, starts_off = 0;
     std::vector<std::function<int()>> fns;
     std::vector<int> fn_grid;  // the grid of each of fns
+    std::vector<int> key;      // plan position (launches of one position touch disjoint grids)
   };
   bool planned = false;
   std::vector<Launch> plan[2];
@@ -2307,6 +2308,7 @@ int batch_plan(dgmg_batch* b, bool fill) {
       while (j < v.size() && v[j].key == v[i].key && sig(v[j]) == sig(v[i])) ++j;
       dgmg_batch::Launch ln;
       ln.kind = v[i].kind;
+      ln.key = v[i].key;
       ln.dim = v[i].dim;
       ln.f32 = v[i].f32;
       for (int k = 0; k < 4; ++k) ln.t[k] = v[i].t[k];
@@ -2364,43 +2366,59 @@ int run_launch_t(dgmg_batch* b, const dgmg_batch::Launch& ln, hipStream_t s) {
 // skip_done: leave out the per-grid operations of grids that have converged
 // (eager runs; a recorded graph keeps them, and their kernels return at once)
 int run_plan(dgmg_batch* b, int which, hipStream_t s, bool skip_done) {
+  const auto& plan = b->plan[which];
   std::vector<int> act;
-  for (const auto& ln : b->plan[which]) {
-    int rc;
-    if (ln.kind == BK_FN) {
+  for (size_t i0 = 0; i0 < plan.size();) {
+    // the launches of one plan position touch disjoint grids: with side
+    // streams, the per-grid steps (round robin over the side streams) overlap
+    // the position's work-list launches on s, joined before the next position
+    size_t i1 = i0 + 1;
+    while (i1 < plan.size() && plan[i1].key == plan[i0].key) ++i1;
+    int used = 0;  // side streams forked at this position
+    for (size_t li = i0; li < i1; ++li) {
+      const auto& ln = plan[li];
+      if (ln.kind != BK_FN) continue;
       act.clear();
       for (size_t k = 0; k < ln.fns.size(); ++k)
         if (!skip_done || b->flags_host[ln.fn_grid[k]]) act.push_back((int)k);
       const int ns = b->concurrent ? std::min<int>(b->nside, (int)act.size()) : 0;
-      if (ns < 2) {
-        for (int k : act)
-          if ((rc = ln.fns[k]())) return rc;
+      if (ns == 0) {
+        for (int k : act) {
+          int rc = ln.fns[k]();
+          if (rc) return rc;
+        }
         continue;
       }
-      // different grids' steps are independent: round robin over the side
-      // streams, each grid's kernels in order on its stream
-      if (hipEventRecord(b->ev_fork, s) != hipSuccess) return DGMG_EHIP;
-      for (int i = 0; i < ns; ++i)
-        if (hipStreamWaitEvent(b->side[i], b->ev_fork, 0) != hipSuccess) return DGMG_EHIP;
+      if (used == 0) {
+        if (hipEventRecord(b->ev_fork, s) != hipSuccess) return DGMG_EHIP;
+        for (int i = 0; i < b->nside; ++i)
+          if (hipStreamWaitEvent(b->side[i], b->ev_fork, 0) != hipSuccess) return DGMG_EHIP;
+        used = b->nside;
+      }
       for (size_t j = 0; j < act.size(); ++j) {
         dgmg_handle* h = b->h[ln.fn_grid[act[j]]];
         const hipStream_t keep = h->stream;
         h->stream = b->side[j % ns];
-        rc = ln.fns[act[j]]();
+        const int rc = ln.fns[act[j]]();
         h->stream = keep;
         if (rc) return rc;
       }
-      for (int i = 0; i < ns; ++i) {
-        if (hipEventRecord(b->ev_join[i], b->side[i]) != hipSuccess) return DGMG_EHIP;
-        if (hipStreamWaitEvent(s, b->ev_join[i], 0) != hipSuccess) return DGMG_EHIP;
-      }
-      continue;
     }
-    if (ln.f32) rc = ln.dim == 3 ? run_launch_t<float, 3>(b, ln, s) : run_launch_t<float, 2>(b, ln, s);
-    else rc = ln.dim == 3 ? run_launch_t<double, 3>(b, ln, s) : run_launch_t<double, 2>(b, ln, s);
-    if (rc) return DGMG_EUNSUPPORTED;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return DGMG_EHIP;
+    for (size_t li = i0; li < i1; ++li) {
+      const auto& ln = plan[li];
+      if (ln.kind == BK_FN) continue;
+      int rc;
+      if (ln.f32) rc = ln.dim == 3 ? run_launch_t<float, 3>(b, ln, s) : run_launch_t<float, 2>(b, ln, s);
+      else rc = ln.dim == 3 ? run_launch_t<double, 3>(b, ln, s) : run_launch_t<double, 2>(b, ln, s);
+      if (rc) return DGMG_EUNSUPPORTED;
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return DGMG_EHIP;
+    }
+    for (int i = 0; i < used; ++i) {
+      if (hipEventRecord(b->ev_join[i], b->side[i]) != hipSuccess) return DGMG_EHIP;
+      if (hipStreamWaitEvent(s, b->ev_join[i], 0) != hipSuccess) return DGMG_EHIP;
+    }
+    i0 = i1;
   }
   return DGMG_OK;
 }
