@@ -215,3 +215,38 @@ def test_unplanned_batch_matches_single(graphs):
             S.close()
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_with_large_grids_matches_single(graphs):
+    """Two grids whose top level fills the GPU alone (>= 2^20 unknowns: their
+    large-level steps run as per-grid steps on the side streams, overlapping the
+    small grids' work-list launches) next to three small grids: every grid's
+    solution equals its single-grid solve bit for bit, eager and replayed."""
+    probs = [(rand_grid(3, (12, 12, 12), seed=47), synth.Method(P=8, smoother="FA")),
+             (rand_grid(3, (2, 3, 2), seed=48), synth.Method(P=4, smoother="FA")),
+             (rand_grid(3, (11, 12, 12), seed=49), synth.Method(P=8, smoother="EA")),
+             (rand_grid(3, (3, 2, 2), seed=50), synth.Method(P=6, smoother="EA")),
+             (rand_grid(3, (2, 2, 3), seed=51), synth.Method(P=8, smoother="FA"))]
+    B = D.BatchSolver(probs)
+    try:
+        assert B.plan_info()[0] is True
+        big = [B.offsets[i + 1] - B.offsets[i] >= 1 << 20 for i in range(len(probs))]
+        assert big == [True, False, True, False, False]
+        B.use_graphs(graphs)
+        f_all = np.random.default_rng(7).uniform(-1, 1, B.n_dof)
+        x_all = _dev(np.zeros(B.n_dof))
+        for _ in range(2):  # a second solve replays the recorded phases
+            x_all.zero_()
+            stats = B.solve(_dev(f_all), x_all)
+        xb = x_all.cpu().numpy()
+        for i, (g, m) in enumerate(probs):
+            sl = slice(B.offsets[i], B.offsets[i + 1])
+            S = D.Solver(g, m)
+            xs = _dev(np.zeros(sl.stop - sl.start))
+            st = S.solve(_dev(f_all[sl]), xs)
+            assert stats[i]["converged"] and st["iterations"] == stats[i]["iterations"], i
+            assert np.array_equal(xs.cpu().numpy(), xb[sl]), i
+            S.close()
+    finally:
+        B.close()
