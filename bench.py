@@ -286,11 +286,27 @@ def _extra_workload(name, args):
     res = {}
     for prec in ("mixed", "fp64"):
         _log(f"{name}: {prec}")
-        S = dgmg.Solver(w.grid, synth.with_method(w, precision=prec).method, max_iter=200)
+        mw = synth.with_method(w, precision=prec).method
+        S = dgmg.Solver(w.grid, mw, max_iter=200)
         if not args.no_autotune:
             S.autotune()
         sec, ent = _solve_entry(S, rhs, x, w.tol, args.warmup, max(2, args.steps // 2))
         ent["value"] = n / sec
+        # top-level patch solve: its mean launch time (HIP events, one extra solve)
+        # against the method's flop count per unknown, in the handle's precision
+        S.kernel_timing(True)
+        x.zero_()
+        S.solve(rhs, x, w.tol)
+        kt = S.kernel_time()
+        S.kernel_timing(False)
+        L = S.num_levels - 1
+        P, n_o, nl = S.level_info(L)
+        k_ms = kt["ms"] / max(kt["launches"], 1)
+        fl = sweep_flops_per_dof(w.grid.dim, P, n_o, mw.smoother) * nl
+        peak = FP64_VALU_PEAK_TFLOPS if prec == "fp64" else FP32_MFMA_PEAK_TFLOPS
+        ent["patch_solve"] = {"kernel": _top_kernel(S, mw)[0], "avg_ms": k_ms, "launches": kt["launches"],
+                              "flops_per_launch": fl, "achieved_TFLOPs": fl / (k_ms * 1e-3) / 1e12,
+                              "peak_TFLOPs": peak, "frac": fl / (k_ms * 1e-3) / 1e12 / peak}
         res[prec] = sec
         out[prec] = ent
         if prec == "mixed" and name == "c5" and w.method.smoother == "FA":
