@@ -184,6 +184,155 @@ __global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* _
   for (int q = tid; q < ne * NE; q += nth) w[(int64_t)e0 * NE + q] = acc[q];
 }
 
+// y = A x (MODE 0) or y = f - A x (MODE 1) in one launch, each element
+// computing the lattice nodes it owns (local index below P in every
+// direction: every node has exactly one owner).  Per direction the assembled
+// 1D row at an owned node is the element's own row of (2/dx) L^s, plus at its
+// first node (shared with the left neighbour along that direction) row P of
+// the neighbour's, whose line is read from global memory (L2); the other
+// directions contribute the assembled lumped masses.  Own closed element tiles
+// are staged in LDS; one pass per direction with a thread per line (rows of
+// L^s as uniform operands), accumulated in LDS in direction order.
+template <int NP, int DIM>
+constexpr int se_owned_epb() {  // about 256 lines per pass, tiles within about 96 KB of LDS
+  return imax(1, imin(256 / ipow(NP - 1, DIM - 1), 96 * 1024 / ((ipow(NP, DIM) + ipow(NP - 1, DIM)) * 8)));
+}
+template <class T, int DIM, int NP>
+__global__ void __launch_bounds__(256) se_owned_kernel(LevelDev<T> L, int mode, const T* __restrict__ x,
+                                                       const T* __restrict__ f, T* __restrict__ y, int nblk,
+                                                       int epb) {
+  constexpr int P = NP - 1, NE = ipow(NP, DIM), NO_ = ipow(P, DIM), NLN = ipow(P, DIM - 1);
+  constexpr int EPB = se_owned_epb<NP, DIM>();
+  __shared__ T xs[EPB * NE];
+  __shared__ T acc[EPB * NO_];
+  __shared__ int64_t off[EPB][3][NP];   // own closed tile
+  __shared__ int64_t offl[EPB][3][NP];  // left neighbour's nodes along each direction (-1: none)
+  __shared__ T mass[EPB][3][NP];        // assembled lumped mass at local index i < P
+  __shared__ T two[EPB][3], twol[EPB][3];
+  constexpr bool SLS = NP * sizeof(T) <= 72;
+  __shared__ T sLs[SLS ? 1 : NP * NP];
+  const int blk = xcd_block(nblk);
+  if (blk < 0 || inactive(L.active)) return;
+  const int e0 = blk * epb, ne = imin(imin(epb, EPB), L.n_elem - e0);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (!SLS)
+    for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
+  const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  int64_t st[3];
+  se_strides(L, st);
+  for (int q = tid; q < ne * 3 * NP; q += nth) {
+    const int el = q / (3 * NP), rem = q - el * 3 * NP, d = rem / NP, i = rem - d * NP;
+    const int e = e0 + el;
+    if (d >= DIM) {
+      off[el][d][i] = offl[el][d][i] = 0;
+      mass[el][d][i] = T(1);
+      if (i == 0) two[el][d] = twol[el][d] = T(0);
+      continue;
+    }
+    const int md = d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
+    const DirDev<T>& dd = L.dir[d];
+    const bool hasl = dd.periodic || md > 0;
+    const int ml = md == 0 ? dd.N - 1 : md - 1;
+    const int s0 = se_stored(md * P + i, P, dd.N, dd.periodic);
+    off[el][d][i] = s0 < 0 ? -1 : s0 * st[d];
+    const int s1 = hasl ? se_stored(ml * P + i, P, dd.N, dd.periodic) : -1;
+    offl[el][d][i] = s1 < 0 ? -1 : s1 * st[d];
+    const T h = dd.ecoef[md * ECOEF_N + E_HALF_DX];
+    T mv = h * L.rho[i];
+    if (i == 0 && hasl) mv += dd.ecoef[ml * ECOEF_N + E_HALF_DX] * L.rho[P];
+    mass[el][d][i] = mv;
+    if (i == 0) {
+      two[el][d] = dd.ecoef[md * ECOEF_N + E_TWO_DX];
+      twol[el][d] = hasl ? dd.ecoef[ml * ECOEF_N + E_TWO_DX] : T(0);
+    }
+  }
+  __syncthreads();
+  constexpr int GU = 8;
+  for (int q0 = tid; q0 < ne * NE; q0 += GU * nth) {
+    T v[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int q = q0 + u * nth;
+      const int qq = q < ne * NE ? q : 0;
+      const int el = qq / NE, loc = qq - el * NE;
+      const int i = loc % NP, j = (loc / NP) % NP, k = DIM == 3 ? loc / (NP * NP) : 0;
+      const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
+      const bool ok = q < ne * NE && (a | b | c) >= 0;
+      T t = T(0);
+      if (ok) t = x[a + b + c];
+      v[u] = t;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+      if (q0 + u * nth < ne * NE) xs[q0 + u * nth] = v[u];
+  }
+  __syncthreads();
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Ls = (CT*)L.Ls;
+#pragma unroll 1
+  for (int d = 0; d < DIM; ++d) {
+    const int stn = d == 0 ? 1 : (d == 1 ? NP : NP * NP);  // stride of direction d in the closed tile
+    const int sto = d == 0 ? 1 : (d == 1 ? P : P * P);     // ... in the owned tile
+    for (int q = tid; q < ne * NLN; q += nth) {
+      const int el = q / NLN, ln = q - el * NLN;
+      const int o1 = ln % P, o2 = DIM == 3 ? ln / P : 0;  // the other directions' indices, increasing order
+      int basen, baseo, da, db;
+      if (d == 0) {
+        basen = (o2 * NP + o1) * NP, baseo = (o2 * P + o1) * P, da = 1, db = 2;
+      } else if (d == 1) {
+        basen = o2 * NP * NP + o1, baseo = o2 * P * P + o1, da = 0, db = 2;
+      } else {
+        basen = o2 * NP + o1, baseo = o2 * P + o1, da = 0, db = 1;
+      }
+      T fac = mass[el][da][o1];
+      if (DIM == 3) fac *= mass[el][db][o2];
+      const T* src = xs + el * NE + basen;
+      T v[NP];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) v[a] = src[a * stn];
+      // row P of the left neighbour at the shared first node
+      // (there is one exactly when the shared node is stored; the neighbour's own
+      // first node may be a dropped Dirichlet node, which reads as 0)
+      T left = T(0);
+      {
+        const int64_t oa = off[el][da][o1], ob = DIM == 3 ? off[el][db][o2] : 0;
+        const bool okl = offl[el][d][P] >= 0 && (oa | ob) >= 0;
+        if (okl) {
+          const T* xl = x + oa + ob;
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            const int64_t oo = offl[el][d][a];
+            T xv = T(0);
+            if (oo >= 0) xv = xl[oo];
+            left += (SLS ? (T)Ls[P * NP + a] : sLs[P * NP + a]) * xv;
+          }
+          left *= twol[el][d];
+        }
+      }
+      T* dst = acc + el * NO_ + baseo;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) s += (SLS ? (T)Ls[i * NP + a] : sLs[i * NP + a]) * v[a];
+        s *= two[el][d];
+        if (i == 0) s += left;
+        s *= fac;
+        dst[i * sto] = d == 0 ? s : dst[i * sto] + s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < ne * NO_; q += nth) {
+    const int el = q / NO_, loc = q - el * NO_;
+    const int i = loc % P, j = (loc / P) % P, k = DIM == 3 ? loc / (P * P) : 0;
+    const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
+    if ((a | b | c) < 0) continue;
+    const int64_t g = a + b + c;
+    y[g] = mode == 1 ? f[g] - acc[q] : acc[q];
+  }
+}
+
 // Lattice node q of level L: per direction the (element, local node) pairs of
 // the elements sharing it (two at an element boundary, else one).
 template <class T, int DIM>
@@ -439,6 +588,17 @@ int se_apply_launch(const LevelDev<T>& L, int mode, const T* x, const T* f, T* y
     return -4;  // element tiles beyond LDS
   } else {
     if (mode != 0 && mode != 1) return -4;
+    // owner-computes form (one launch, no element copies) on levels with many
+    // lines; small levels keep the two-launch form, whose thread-per-output
+    // variant has more parallel work
+    if (NP >= 3 && (int64_t)L.n_elem * ipow(NP - 1, DIM - 1) >= 64 * 1024) {
+      constexpr int EPBO = se_owned_epb<NP, DIM>();
+      const int epb = imax(1, imin(EPBO, L.n_elem / 512));
+      const int nb = (L.n_elem + epb - 1) / epb;
+      hipLaunchKernelGGL((se_owned_kernel<T, DIM, NP>), dim3(xcd_grid(nb)), dim3(256), 0, s, L, mode, x, f, y, nb,
+                         epb);
+      return 0;
+    }
     // elements per block: up to se_epb, fewer on small levels so that the
     // launch still has about 512 blocks
     constexpr int EPB = se_epb<NP, DIM>(), NLN = ipow(NP, DIM - 1);

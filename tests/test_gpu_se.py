@@ -285,3 +285,33 @@ def test_fullsize_mixed_solve_reaches_the_true_residual():
         assert rn <= bound, (rn, bound)
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("dim,n,periodic,P", [(3, (12, 11, 10), (False, True, False), 8),
+                                              (2, (64, 64), (True, False), 16),
+                                              (3, (17, 16, 16), True, 4)])
+def test_owner_computes_operator_on_large_levels(dim, n, periodic, P):
+    """Levels with at least 64k element lines take the one-launch owner-computes
+    operator (the parity grids above are smaller and take the two-launch form):
+    y = A x and r = f - A x against the oracle's matrix-free operator, FP64 within
+    1e-12 and FP32 within its rounding bound, on every level."""
+    g = rand_grid(dim, n, periodic=periodic, seed=60 + P)
+    m = synth.Method(P=P, smoother="EA", disc="se")
+    print(f"[case owned {dim}d {n} P={P}]", flush=True)
+    S = D.Solver(g, m)
+    try:
+        rng = np.random.default_rng(61)
+        from oracle.multigrid import level_orders
+        for l, Pl in enumerate(level_orders(P)):
+            nl = se.n_dof(g, Pl)
+            x, f = rng.standard_normal((2, nl))
+            ref = se.apply_kron(g, Pl, x)
+            assert _rel(_host(S.apply(l, _dev(x))), ref) < 1e-12, l
+            assert _rel(_host(S.residual(l, _dev(f), _dev(x))), f - ref) < 1e-12, l
+            x32 = x.astype(np.float32).astype(np.float64)
+            ops = [se.assemble_1d(Pl, g.dx[d], g.periodic[d]) for d in range(dim)]
+            ax = se.apply_kron(g, Pl, np.abs(x32), ops=[(M, np.abs(Lm)) for M, Lm in ops])
+            y32 = _host(S.apply(l, _dev(x32, torch.float32)))
+            assert np.all(np.abs(y32 - se.apply_kron(g, Pl, x32)) <= 64 * np.finfo(np.float32).eps * ax + 1e-30), l
+    finally:
+        S.close()
