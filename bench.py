@@ -469,8 +469,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of MB MiB (PMC calibration) and exit")
-    ap.add_argument("--se-only", action="store_true",
-                    help="only the continuous spectral-element entry (for profiling), printed as its own JSON line")
+    ap.add_argument("--workload", choices=["c3", "c4", "c4_small", "c5", "se"], default=None,
+                    help="only this extra entry (for profiling), printed as its own JSON line: c3, c5 (mixed "
+                         "and FP64), c4 / c4_small (batched against one by one), se (continuous counterpart)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the solver "
@@ -480,8 +481,14 @@ def main():
     if args.copy_calibration:
         _copy_calibration(args.copy_calibration)
         return
-    if args.se_only:
-        print(json.dumps({"spectral_element": _se_entry(args)}), flush=True)
+    if args.workload:
+        if args.workload in ("c3", "c5"):
+            ent = _extra_workload(args.workload, args)
+        elif args.workload in ("c4", "c4_small"):
+            ent = _batched_entry(args, small=args.workload == "c4_small")
+        else:
+            ent = _se_entry(args)
+        print(json.dumps({args.workload: ent}), flush=True)
         return
 
     import torch
