@@ -303,7 +303,12 @@ const char* dgmg_last_error(const dgmg_handle* h);
  * at one position that use the same kernel instance (order, tile, mode) run as
  * ONE launch over all those grids' elements or patches, with per-grid
  * argument descriptors in the workspace; vector updates, fills and coarse
- * solves stay per grid.  Otherwise each grid's chain is issued on its own.
+ * solves stay per grid.  When a grid's top level has at least 2^20 unknowns
+ * (its levels that large keep their own launches), the per-grid steps of one
+ * position run round robin on three side streams the batch creates at bind
+ * (default priority; forked from and joined back into the batch stream by
+ * events) and overlap that position's shared launches; results do not depend
+ * on it.  Otherwise each grid's chain is issued on its own.
  * Either way a phase is issued eagerly (the default; the per-grid
  * operations of converged grids are then left out) or captured once as a
  * hipGraph and replayed.  Vectors of all grids are
@@ -317,7 +322,9 @@ int dgmg_batch_workspace_bytes(const dgmg_batch* b, size_t* bytes);
  * run as work-list plans; kernels = batched launches per MGCG iteration (both
  * phases), grid_ops = per-grid operations per iteration. */
 int dgmg_batch_plan_info(const dgmg_batch* b, int* planned, int* kernels, int* grid_ops);
-/* Bind one caller-allocated device workspace (256-byte aligned) for all grids. */
+/* Bind one caller-allocated device workspace (256-byte aligned) for all grids;
+ * a planned batch also creates its three side streams and their events here
+ * (released by dgmg_batch_destroy).  DGMG_EHIP if they cannot be created. */
 int dgmg_batch_bind_workspace(dgmg_batch* b, void* dev, size_t bytes, void* stream);
 /* Host array of count + 1 offsets of each grid's unknowns in the concatenation. */
 int dgmg_batch_offsets(const dgmg_batch* b, int64_t* offsets);
