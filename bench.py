@@ -111,6 +111,11 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# every TIMING_STRIDE-th top-level patch-solve launch of the timed solves carries an
+# event pair (a stride prime to the sweep count samples every sweep normal alike)
+TIMING_STRIDE = 5
+
+
 def _time_solves(S, rhs, x, tol, warmup, steps, timing):
     import torch
     st = None
@@ -119,7 +124,7 @@ def _time_solves(S, rhs, x, tol, warmup, steps, timing):
         st = S.solve(rhs, x, tol)
     torch.cuda.synchronize()
     if timing:
-        S.kernel_timing(True)
+        S.kernel_timing(True, stride=TIMING_STRIDE)
     t0 = time.perf_counter()
     for _ in range(steps):
         x.zero_()
@@ -172,6 +177,7 @@ def _dominant_roofline(S, m, kt, word):
     kname, _ = _top_kernel(S, m)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "kernel": kname, "avg_ms": k_ms, "launches": kt["launches"],
+            "launch_sampling_stride": TIMING_STRIDE,
             "flops_per_launch": flops, "flops_per_dof": flops / n,
             "alg_bytes_per_launch": alg_bytes, "alg_GBps": alg_bytes / (k_ms * 1e-3) / 1e9,
             "hbm_GBps": None if traffic is None else traffic / (k_ms * 1e-3) / 1e9,

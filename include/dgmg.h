@@ -259,11 +259,13 @@ int dgmg_solve(dgmg_handle* h, const double* rhs, double* x, double tol, dgmg_st
  * vectors of the top level; continuous handles: the assembled lumped mass). */
 int dgmg_mass(dgmg_handle* h, const double* f_nodal, double* g);
 
-/* Per-kernel timing with HIP events on the handle's stream.  enable != 0
- * starts recording the Schwarz patch-solve kernel launches (and clears the
- * totals); dgmg_kernel_time reads, after synchronisation, the summed
- * milliseconds, launch count and algorithmic flops and bytes of those
- * launches (host outputs; NULL allowed). */
+/* Per-kernel timing with HIP events on the handle's stream.  enable = k >= 1
+ * starts recording the top-level Schwarz patch-solve launches, every k-th one
+ * (1: every launch; a stride keeps the event overhead out of most launches,
+ * and a stride prime to the number of sweep normals samples them all), and
+ * clears the totals; 0 stops.  dgmg_kernel_time reads, after synchronisation,
+ * the summed milliseconds, launch count and algorithmic flops and bytes of the
+ * recorded launches (host outputs; NULL allowed). */
 int dgmg_kernel_timing(dgmg_handle* h, int enable);
 int dgmg_kernel_time(dgmg_handle* h, double* total_ms, int64_t* launches, double* flops,
                      double* bytes);

@@ -408,8 +408,11 @@ struct dgmg_handle {
   // autotuned patch-solve block shapes (waves per block), 0 = default
   int waves[MAXL][NKIND] = {};
   float tune_ms[MAXL][NKIND] = {};
-  // timing of the top-level patch solves
+  // timing of the top-level patch solves: every timing_stride-th launch
+  // (counted in timing_count) carries an event pair
   bool timing = false;
+  int timing_stride = 1;
+  int64_t timing_count = 0;
   // V-cycle residual + restriction in one launch where built; the environment
   // variable DGMG_NO_FUSED_RESTRICTION at setup selects the two-step path
   // (same values; kept for comparison)
@@ -844,7 +847,8 @@ int k_sweep(dgmg_handle* h, int l, int nd, T* u, const T* f, T* r, bool u_zero =
   sweep_shape(lv, nd, np, NA, NL);
   const int kind = nd < 0 ? 3 : nd;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = h->timing && l == (int)h->lv.size() - 1;  // top-level launches only
+  // top-level launches only, every timing_stride-th of them
+  const bool timed = h->timing && l == (int)h->lv.size() - 1 && (h->timing_count++ % h->timing_stride) == 0;
   if (timed) {
     e0 = take_event(h);
     e1 = take_event(h);
@@ -1759,6 +1763,7 @@ int dgmg_tune_set(dgmg_handle* h, int level, int kind, int waves) {
 
 int dgmg_kernel_timing(dgmg_handle* h, int enable) {
   if (!h) return DGMG_EINVAL;
+  if (enable < 0) return fail(h, DGMG_EINVAL, "kernel timing: negative stride");
   for (auto& e : h->ev) {
     h->ev_pool.push_back(e.first);
     h->ev_pool.push_back(e.second);
@@ -1780,6 +1785,8 @@ int dgmg_kernel_timing(dgmg_handle* h, int enable) {
   h->t_ms = h->t_flops = h->t_bytes = 0;
   h->t_launch = 0;
   h->timing = enable != 0;
+  h->timing_stride = enable > 1 ? enable : 1;
+  h->timing_count = 0;
   return DGMG_OK;
 }
 

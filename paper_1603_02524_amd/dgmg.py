@@ -336,8 +336,11 @@ class Solver:
     def set_tuning(self, level, kind, waves):
         self._check(self.lib.dgmg_tune_set(self.h, level, kind, int(waves)))
 
-    def kernel_timing(self, enable=True):
-        self._check(self.lib.dgmg_kernel_timing(self.h, int(enable)))
+    def kernel_timing(self, enable=True, stride=1):
+        """Start (every stride-th top-level patch-solve launch timed) or stop."""
+        if enable and stride < 1:
+            raise ValueError("kernel_timing: stride must be >= 1")
+        self._check(self.lib.dgmg_kernel_timing(self.h, int(stride) if enable else 0))
 
     def kernel_time(self):
         ms, n, fl, by = c_double(), c_int64(), c_double(), c_double()

@@ -300,6 +300,12 @@ def test_kernel_timing_of_top_level_patch_solves():
             assert kt["launches"] == 6 * k
             assert kt["ms"] > 0
             assert kt["flops"] == pytest.approx(2 * k * patches * per_launch, rel=1e-12)
+        S.kernel_timing(True, stride=5)  # every fifth launch, the first included
+        st = S.solve(f, _dev(np.zeros(n)))
+        kt = S.kernel_time()
+        S.kernel_timing(False)
+        assert kt["launches"] == -(-6 * st["iterations"] // 5)
+        assert kt["ms"] > 0
         S.solve(f, _dev(np.zeros(n)))  # timing off: nothing recorded
         assert S.kernel_time()["launches"] == 0
     finally:
