@@ -189,47 +189,56 @@ __global__ void __launch_bounds__(1024) se_elem_kernel(LevelDev<T> L, const T* _
 // direction: every node has exactly one owner).  Per direction the assembled
 // 1D row at an owned node is the element's own row of (2/dx) L^s, plus at its
 // first node (shared with the left neighbour along that direction) row P of
-// the neighbour's, whose line is read from global memory (L2); the other
-// directions contribute the assembled lumped masses.  Own closed element tiles
-// are staged in LDS; one pass per direction with a thread per line (rows of
-// L^s as uniform operands), accumulated in LDS in direction order.
+// the neighbour's, applied to the neighbour's line read from global memory
+// (L2); the other directions contribute the assembled lumped masses.  The
+// element's closed tile is staged in LDS; then one thread per owned column
+// along the last direction computes all DIM directional terms of the column's
+// nodes (its own column with the rows of L^s as uniform operands, the other
+// directions' lines from the tile with the thread's fixed rows in registers),
+// so no partial sums go through LDS and the block needs only the tile.
 template <int NP, int DIM>
-constexpr int se_owned_epb() {  // about 256 lines per pass, tiles within about 96 KB of LDS
-  return imax(1, imin(256 / ipow(NP - 1, DIM - 1), 96 * 1024 / ((ipow(NP, DIM) + ipow(NP - 1, DIM)) * 8)));
+constexpr int se_owned_bytes() {  // LDS per element
+  return (ipow(NP, DIM) + DIM * ipow(NP - 1, DIM - 1)) * 8 + 3 * NP * 24 + 24;
+}
+template <int NP, int DIM>
+constexpr int se_owned_epb() {  // a thread per owned column, 256 threads, within 64 KB of LDS
+  return imax(1, imin(256 / ipow(NP - 1, DIM - 1), 64 * 1024 / se_owned_bytes<NP, DIM>()));
 }
 template <class T, int DIM, int NP>
 __global__ void __launch_bounds__(256) se_owned_kernel(LevelDev<T> L, int mode, const T* __restrict__ x,
                                                        const T* __restrict__ f, T* __restrict__ y, int nblk,
                                                        int epb) {
-  constexpr int P = NP - 1, NE = ipow(NP, DIM), NO_ = ipow(P, DIM), NLN = ipow(P, DIM - 1);
+  constexpr int P = NP - 1, NE = ipow(NP, DIM), NLN = ipow(P, DIM - 1);
   constexpr int EPB = se_owned_epb<NP, DIM>();
+  static_assert(EPB * NLN <= 256, "one owned column per thread of a 256-thread block");
   __shared__ T xs[EPB * NE];
-  __shared__ T acc[EPB * NO_];
+  __shared__ T lft[EPB][DIM][NLN];      // neighbour terms at the owned first nodes, per direction
   __shared__ int64_t off[EPB][3][NP];   // own closed tile
   __shared__ int64_t offl[EPB][3][NP];  // left neighbour's nodes along each direction (-1: none)
   __shared__ T mass[EPB][3][NP];        // assembled lumped mass at local index i < P
-  __shared__ T two[EPB][3], twol[EPB][3];
-  constexpr bool SLS = NP * sizeof(T) <= 72;
-  __shared__ T sLs[SLS ? 1 : NP * NP];
+  __shared__ T two[EPB][3];
+  __shared__ T sLs[NP * NP];
   const int blk = xcd_block(nblk);
   if (blk < 0 || inactive(L.active)) return;
   const int e0 = blk * epb, ne = imin(imin(epb, EPB), L.n_elem - e0);
   const int tid = threadIdx.x, nth = blockDim.x;
-  if constexpr (!SLS)
-    for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
+  for (int q = tid; q < NP * NP; q += nth) sLs[q] = L.Ls[q];
   const int N1 = L.dir[0].N, N2 = L.dir[1].N;
+  // element index along direction d of element e
+  const auto mdir = [&](int e, int d) -> int {
+    return d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
+  };
   int64_t st[3];
   se_strides(L, st);
+  // lattice offsets of the closed tile's nodes and of the left neighbour's
+  // (integer work only, so the gather can start after one barrier)
   for (int q = tid; q < ne * 3 * NP; q += nth) {
     const int el = q / (3 * NP), rem = q - el * 3 * NP, d = rem / NP, i = rem - d * NP;
-    const int e = e0 + el;
     if (d >= DIM) {
       off[el][d][i] = offl[el][d][i] = 0;
-      mass[el][d][i] = T(1);
-      if (i == 0) two[el][d] = twol[el][d] = T(0);
       continue;
     }
-    const int md = d == 0 ? e % N1 : (d == 1 ? (DIM == 3 ? (e / N1) % N2 : e / N1) : e / (N1 * N2));
+    const int md = mdir(e0 + el, d);
     const DirDev<T>& dd = L.dir[d];
     const bool hasl = dd.periodic || md > 0;
     const int ml = md == 0 ? dd.N - 1 : md - 1;
@@ -237,17 +246,66 @@ __global__ void __launch_bounds__(256) se_owned_kernel(LevelDev<T> L, int mode, 
     off[el][d][i] = s0 < 0 ? -1 : s0 * st[d];
     const int s1 = hasl ? se_stored(ml * P + i, P, dd.N, dd.periodic) : -1;
     offl[el][d][i] = s1 < 0 ? -1 : s1 * st[d];
-    const T h = dd.ecoef[md * ECOEF_N + E_HALF_DX];
-    T mv = h * L.rho[i];
-    if (i == 0 && hasl) mv += dd.ecoef[ml * ECOEF_N + E_HALF_DX] * L.rho[P];
-    mass[el][d][i] = mv;
-    if (i == 0) {
-      two[el][d] = dd.ecoef[md * ECOEF_N + E_TWO_DX];
-      twol[el][d] = hasl ? dd.ecoef[ml * ECOEF_N + E_TWO_DX] : T(0);
-    }
   }
+  // assembled lumped masses and 2/dx factors (global loads: issued behind the
+  // gather's first group)
+  const auto coef_tables = [&]() {
+    for (int q = tid; q < ne * 3 * NP; q += nth) {
+      const int el = q / (3 * NP), rem = q - el * 3 * NP, d = rem / NP, i = rem - d * NP;
+      if (d >= DIM) {
+        mass[el][d][i] = T(1);
+        if (i == 0) two[el][d] = T(0);
+        continue;
+      }
+      const int md = mdir(e0 + el, d);
+      const DirDev<T>& dd = L.dir[d];
+      const bool hasl = dd.periodic || md > 0;
+      const int ml = md == 0 ? dd.N - 1 : md - 1;
+      const T h = dd.ecoef[md * ECOEF_N + E_HALF_DX];
+      T mv = h * L.rho[i];
+      if (i == 0 && hasl) mv += dd.ecoef[ml * ECOEF_N + E_HALF_DX] * L.rho[P];
+      mass[el][d][i] = mv;
+      if (i == 0) two[el][d] = dd.ecoef[md * ECOEF_N + E_TWO_DX];
+    }
+  };
   __syncthreads();
-  constexpr int GU = 8;
+  using CT = const __attribute__((address_space(4))) T;
+  CT* __restrict__ Ls = (CT*)L.Ls;
+  // neighbour term of direction d at owned face node (o1, o2) of the other
+  // directions (increasing order): twol * (row P of L^s) . (the left
+  // neighbour's line), 0 without a stored shared node (the neighbour's own
+  // first node may be a dropped Dirichlet node, which reads as 0).  At most
+  // DIM entries per thread.
+  const auto neighbour_terms = [&]() {
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      const int q = tid + r * nth;
+      if (q >= ne * DIM * NLN) break;
+      const int el = q / (DIM * NLN), rem = q - el * DIM * NLN, d = rem / NLN, fi = rem - d * NLN;
+      const int o1 = fi % P, o2 = DIM == 3 ? fi / P : 0;
+      const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+      T left = T(0);
+      const int64_t oa = off[el][da][o1], ob = DIM == 3 ? off[el][db][o2] : 0;
+      if (offl[el][d][P] >= 0 && (oa | ob) >= 0) {  // a stored shared node: the neighbour exists
+        const DirDev<T>& dd = L.dir[d];
+        const int md = mdir(e0 + el, d), ml = md == 0 ? dd.N - 1 : md - 1;
+        const T twol = dd.ecoef[ml * ECOEF_N + E_TWO_DX];
+        const T* xl = x + oa + ob;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          const int64_t oo = offl[el][d][a];
+          T xv = T(0);
+          if (oo >= 0) xv = xl[oo];
+          left += (T)Ls[P * NP + a] * xv;
+        }
+        left *= twol;
+      }
+      lft[el][d][fi] = left;
+    }
+  };
+  // the closed tiles, GU loads per thread in flight; the neighbour terms' loads
+  // are issued behind the first group's, so both wait on one memory latency
+  constexpr int GU = 12;
   for (int q0 = tid; q0 < ne * NE; q0 += GU * nth) {
     T v[GU];
 #pragma unroll
@@ -262,74 +320,92 @@ __global__ void __launch_bounds__(256) se_owned_kernel(LevelDev<T> L, int mode, 
       if (ok) t = x[a + b + c];
       v[u] = t;
     }
+    if (q0 == tid) {
+      neighbour_terms();
+      coef_tables();
+    }
 #pragma unroll
     for (int u = 0; u < GU; ++u)
       if (q0 + u * nth < ne * NE) xs[q0 + u * nth] = v[u];
   }
+  if (tid >= ne * NE) {  // threads without a tile entry
+    neighbour_terms();
+    coef_tables();
+  }
   __syncthreads();
-  using CT = const __attribute__((address_space(4))) T;
-  CT* __restrict__ Ls = (CT*)L.Ls;
-#pragma unroll 1
-  for (int d = 0; d < DIM; ++d) {
-    const int stn = d == 0 ? 1 : (d == 1 ? NP : NP * NP);  // stride of direction d in the closed tile
-    const int sto = d == 0 ? 1 : (d == 1 ? P : P * P);     // ... in the owned tile
-    for (int q = tid; q < ne * NLN; q += nth) {
-      const int el = q / NLN, ln = q - el * NLN;
-      const int o1 = ln % P, o2 = DIM == 3 ? ln / P : 0;  // the other directions' indices, increasing order
-      int basen, baseo, da, db;
-      if (d == 0) {
-        basen = (o2 * NP + o1) * NP, baseo = (o2 * P + o1) * P, da = 1, db = 2;
-      } else if (d == 1) {
-        basen = o2 * NP * NP + o1, baseo = o2 * P * P + o1, da = 0, db = 2;
-      } else {
-        basen = o2 * NP + o1, baseo = o2 * P + o1, da = 0, db = 1;
+  // thread per owned column along direction DIM - 1: (i, j) in 3D, i in 2D
+  for (int q = tid; q < ne * NLN; q += nth) {
+    const int el = q / NLN, c = q - el * NLN;
+    const T* __restrict__ xe = xs + el * NE;
+    const int i = c % P, j = DIM == 3 ? c / P : 0;
+    T col[NP], Li[NP], Lj[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      col[a] = DIM == 3 ? xe[i + NP * j + NP * NP * a] : xe[i + NP * a];
+      Li[a] = sLs[i * NP + a];
+      Lj[a] = DIM == 3 ? sLs[j * NP + a] : T(0);
+    }
+    const int64_t oi = off[el][0][i], oj = DIM == 3 ? off[el][1][j] : 0;
+    const T mi = mass[el][0][i], mj = DIM == 3 ? mass[el][1][j] : T(1);
+    const T t0 = two[el][0], t1 = two[el][1], tc = two[el][DIM - 1];
+#pragma unroll 2
+    for (int k = 0; k < P; ++k) {  // the column's nodes (its index in direction DIM - 1)
+      // direction 0: row i along (., j, k)
+      T s0 = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) s0 += Li[a] * (DIM == 3 ? xe[a + NP * j + NP * NP * k] : xe[a + NP * k]);
+      s0 *= t0;
+      if (i == 0) s0 += lft[el][0][DIM == 3 ? j + P * k : k];
+      s0 *= DIM == 3 ? mj * mass[el][2][k] : mass[el][1][k];
+      T sum = s0;
+      if constexpr (DIM == 3) {
+        // direction 1: row j along (i, ., k)
+        T s1 = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) s1 += Lj[a] * xe[i + NP * a + NP * NP * k];
+        s1 *= t1;
+        if (j == 0) s1 += lft[el][1][i + P * k];
+        s1 *= mi * mass[el][2][k];
+        sum += s1;
       }
-      T fac = mass[el][da][o1];
-      if (DIM == 3) fac *= mass[el][db][o2];
-      const T* src = xs + el * NE + basen;
-      T v[NP];
+      // the column's own direction: row k (uniform) along the column
+      T sc = T(0);
 #pragma unroll
-      for (int a = 0; a < NP; ++a) v[a] = src[a * stn];
-      // row P of the left neighbour at the shared first node
-      // (there is one exactly when the shared node is stored; the neighbour's own
-      // first node may be a dropped Dirichlet node, which reads as 0)
-      T left = T(0);
-      {
-        const int64_t oa = off[el][da][o1], ob = DIM == 3 ? off[el][db][o2] : 0;
-        const bool okl = offl[el][d][P] >= 0 && (oa | ob) >= 0;
-        if (okl) {
-          const T* xl = x + oa + ob;
-#pragma unroll
-          for (int a = 0; a < NP; ++a) {
-            const int64_t oo = offl[el][d][a];
-            T xv = T(0);
-            if (oo >= 0) xv = xl[oo];
-            left += (SLS ? (T)Ls[P * NP + a] : sLs[P * NP + a]) * xv;
-          }
-          left *= twol[el][d];
-        }
-      }
-      T* dst = acc + el * NO_ + baseo;
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < NP; ++a) s += (SLS ? (T)Ls[i * NP + a] : sLs[i * NP + a]) * v[a];
-        s *= two[el][d];
-        if (i == 0) s += left;
-        s *= fac;
-        dst[i * sto] = d == 0 ? s : dst[i * sto] + s;
+      for (int a = 0; a < NP; ++a) sc += (T)Ls[k * NP + a] * col[a];
+      sc *= tc;
+      if (k == 0) sc += lft[el][DIM - 1][c];
+      sc *= DIM == 3 ? mi * mj : mi;
+      sum += sc;
+      const int64_t ok = off[el][DIM - 1][k];
+      if ((oi | oj | ok) >= 0) {
+        const int64_t g = oi + oj + ok;
+        y[g] = mode == 1 ? f[g] - sum : sum;
       }
     }
-    __syncthreads();
   }
-  for (int q = tid; q < ne * NO_; q += nth) {
-    const int el = q / NO_, loc = q - el * NO_;
-    const int i = loc % P, j = (loc / P) % P, k = DIM == 3 ? loc / (P * P) : 0;
-    const int64_t a = off[el][0][i], b = off[el][1][j], c = off[el][2][k];
-    if ((a | b | c) < 0) continue;
-    const int64_t g = a + b + c;
-    y[g] = mode == 1 ? f[g] - acc[q] : acc[q];
+}
+
+// Stored index per direction of lattice entry q (direction 0 fastest), in
+// 32-bit arithmetic wherever the level's vector allows it: a 64-bit integer
+// division costs several times as many instructions.
+template <class T, int DIM>
+__device__ __forceinline__ void se_split(const LevelDev<T>& L, int64_t q, int s[3]) {
+  s[0] = s[1] = s[2] = 0;
+  if (L.n_dof <= 0x7fffffff) {
+    uint32_t rest = (uint32_t)q;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const uint32_t nl = (uint32_t)L.dir[d].nl;
+      s[d] = (int)(rest % nl);
+      rest /= nl;
+    }
+  } else {
+    int64_t rest = q;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      s[d] = (int)(rest % L.dir[d].nl);
+      rest /= L.dir[d].nl;
+    }
   }
 }
 
@@ -339,15 +415,15 @@ template <class T, int DIM>
 __device__ __forceinline__ void se_node_owners(const LevelDev<T>& L, int64_t q, int cnt[3], int em[3][2],
                                                int lo[3][2]) {
   const int P = L.P;
-  int64_t rest = q;
+  int sd[3];
+  se_split<T, DIM>(L, q, sd);
   for (int d = 0; d < 3; ++d) {
     cnt[d] = 1;
     em[d][0] = 0;
     lo[d][0] = 0;
     if (d >= DIM) continue;
     const DirDev<T>& dd = L.dir[d];
-    const int s = (int)(rest % dd.nl);
-    rest /= dd.nl;
+    const int s = sd[d];
     const int g = dd.periodic ? s : s + 1;
     const int m = g / P, i = g - m * P;
     if (i != 0) {
@@ -417,7 +493,8 @@ __global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, 
   constexpr int CZ = DIM == 3 ? MAXC : 1;
   const int P = L.P, NO = L.NO;
   int cnt[3], pm[3][MAXC], tp[3][MAXC];
-  int64_t rest = q;
+  int sd[3];
+  se_split<T, DIM>(L, q, sd);
   for (int d = 0; d < 3; ++d) {
     cnt[d] = 0;
 #pragma unroll
@@ -427,8 +504,7 @@ __global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, 
       continue;
     }
     const DirDev<T>& dd = L.dir[d];
-    const int s = (int)(rest % dd.nl);
-    rest /= dd.nl;
+    const int s = sd[d];
     const int g = dd.periodic ? s : s + 1;
     const int m0 = g / P;
 #pragma unroll
@@ -437,7 +513,10 @@ __global__ void __launch_bounds__(256) se_combine_kernel(LevelDev<T> L, int NA, 
       const int t = g - (m * P - NO);
       const bool in = t >= 0 && t < NA && cnt[d] < MAXC && (dd.periodic || (m >= 0 && m < dd.N));
       if (in) {
-        pm[d][cnt[d]] = ((m % dd.N) + dd.N) % dd.N;
+        // m lies within two elements of the lattice: wrap by additions
+        int mw = m < 0 ? m + dd.N : m;
+        mw = mw < 0 ? mw + dd.N : (mw >= dd.N ? mw - dd.N : mw);
+        pm[d][cnt[d]] = mw >= dd.N ? mw - dd.N : mw;
         tp[d][cnt[d]] = t;
         ++cnt[d];
       }
