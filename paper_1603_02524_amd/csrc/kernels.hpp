@@ -590,6 +590,11 @@ int apply_batch_launch(int mode, const BatchList<ApplyArgs<T>>& bl, int ntot, hi
 #ifndef DGMG_FDM_PING
 #define DGMG_FDM_PING 1
 #endif
+// FP64: the forward and backward passes of tile dimension 2 fused (the scaled
+// forward results feed the backward product from registers).
+#ifndef DGMG_FDM_FUSE2
+#define DGMG_FDM_FUSE2 1
+#endif
 
 // v / d for d > 0 of moderate magnitude (sums of patch eigenvalues): hardware
 // reciprocal estimate, Newton-Raphson refinement of 1/d, then one residual
@@ -788,6 +793,83 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ t
         T* dst = ok ? tile + base + jc * STRIDE : trash + lane;
         *dst = post(lc, jc, acc[nb][r]);
       }
+  }
+}
+
+// The last forward and the first backward contraction of tile dimension 2
+// in one pass (FP64, lines of at most 16): a line block's forward results,
+// scaled by post(line, j, value), stay in registers as the operand of the
+// backward product instead of going through the tile and a barrier.  The f64
+// result layout makes this possible: lane (li, lk) ends the forward product
+// holding rows j = lk + 4r of its line li, which are exactly the contraction
+// indices k = 4 ks + lk (ks = r) it supplies to the next product.  Rows
+// j >= LEN are set to 0 (the backward matrix is zero there as well).  TAIL
+// as in fdm_pass, for both products (tail, tailb: the last rows of the
+// forward and backward matrices).
+template <int NA, int NL, int DIM, class Post, int BLEN, bool TAIL>
+__device__ __forceinline__ void fdm_pass_fused2(double* __restrict__ tile, double* __restrict__ trash,
+                                                const BOp<double, BLEN>& Bf, const BOp<double, BLEN>& Bb,
+                                                Post post, const double* __restrict__ tail,
+                                                const double* __restrict__ tailb) {
+  using T = double;
+  constexpr int TD = 2;
+  constexpr int LEN = NL;
+  constexpr int LINES = NA * ipow(NL, DIM - 2);
+  constexpr int STRIDE = fdm_pitch<NA>() * NL;
+  constexpr int KS = BOp<T, LEN>::KS, NB = BOp<T, LEN>::NB, MB = (LINES + 15) / 16;
+  static_assert(DIM == 3 && NB == 1 && KS == 4, "lines of 13 to 16 values");
+  static_assert(BOp<T, BLEN>::KS == KS && BOp<T, BLEN>::NB == NB, "operand register shape");
+  using M = Mfma<T>;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int mb = wave; mb < MB; mb += nw) {
+    const int line = mb * 16 + li;
+    const bool lv = line < LINES;
+    const int lc = imin(line, LINES - 1);
+    const int base = fdm_line_base<NA, NL, TD>(lc);
+    typename M::acc_t acc = typename M::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < (TAIL ? KS - 1 : KS); ++ks) {
+      const int k = imin(4 * ks + lk, LEN - 1);
+      acc = M::op(Bf.b[0][ks], tile[base + k * STRIDE], acc);
+    }
+    if constexpr (TAIL) {
+      const T at = tile[base + (LEN - 1) * STRIDE];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = imin(M::row(lk, r), LEN - 1);
+        acc[r] = __builtin_fma(tail[j], at, acc[r]);
+      }
+    }
+    typename M::acc_t out = typename M::acc_t{0, 0, 0, 0};
+    T v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = M::row(lk, r);  // = 4 r + lk: the next product's contraction index
+      const T sv = post(lc, imin(j, LEN - 1), acc[r]);
+      v[r] = j < LEN ? sv : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < (TAIL ? 3 : 4); ++r) out = M::op(Bb.b[0][r], v[r], out);
+    if constexpr (TAIL) {
+      // the last contraction index LEN - 1 = 4 * 3 + 0 is held by lane (li, 0)
+      // in register 3: broadcast it to the line's four lanes, rank-one update
+      const T at = __shfl(v[3], li, 64);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = imin(M::row(lk, r), LEN - 1);
+        out[r] = __builtin_fma(tailb[j], at, out[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = M::row(lk, r);
+      const bool ok = lv && j < LEN;
+      const int jc = imin(j, LEN - 1);
+      T* dst = ok ? tile + base + jc * STRIDE : trash + lane;
+      *dst = out[r];
+    }
   }
 }
 
@@ -1001,6 +1083,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
                         NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
                         BOp<T, NA>::NB == BOp<T, NL>::NB;
   BOp<T, NA> P, Q;
+  // FP64 with lateral lines of 13 to 16: the dimension-2 passes fused
+  constexpr bool FUSE2 = DGMG_FDM_FUSE2 && PING && sizeof(T) == 8 && NL > 12 && NL <= 16;
   // FP64 lateral lines with NL = 1 (mod 4): the last row of each of their
   // four matrices in LDS for the rank-one tail of those passes (in FP32 the
   // 16x16x4 product costs half as much and the tail measured slower)
@@ -1083,11 +1167,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
     fdm_pass<T, NA, NL, DIM, 1, NoPost, NA, TAILK>(tile, trash, Q, NoPost(), sBt[0]);
     __syncthreads();
     Q.template load_as<NL>(bwd[2]);
-    fdm_pass<T, NA, NL, DIM, 2, decltype(scale), NA, TAILK>(tile, trash, P, scale, sBt[1]);
-    __syncthreads();
-    P.template load_as<NL>(bwd[1]);
-    fdm_pass<T, NA, NL, DIM, 2, NoPost, NA, TAILK>(tile, trash, Q, NoPost(), sBt[2]);
-    __syncthreads();
+    if constexpr (FUSE2) {
+      // forward and backward along dimension 2 in one pass (no tile round trip)
+      fdm_pass_fused2<NA, NL, DIM, decltype(scale), NA, TAILK>(tile, trash, P, Q, scale, sBt[1], sBt[2]);
+      P.template load_as<NL>(bwd[1]);
+      __syncthreads();
+    } else {
+      fdm_pass<T, NA, NL, DIM, 2, decltype(scale), NA, TAILK>(tile, trash, P, scale, sBt[1]);
+      __syncthreads();
+      P.template load_as<NL>(bwd[1]);
+      fdm_pass<T, NA, NL, DIM, 2, NoPost, NA, TAILK>(tile, trash, Q, NoPost(), sBt[2]);
+      __syncthreads();
+    }
     Q.template load_as<NA>(bwd[0]);
     fdm_pass<T, NA, NL, DIM, 1, NoPost, NA, TAILK>(tile, trash, P, NoPost(), sBt[3]);
     __syncthreads();
