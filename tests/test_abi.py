@@ -106,6 +106,19 @@ def test_level_series_and_geometry_match_oracle():
                 lib.dgmg_destroy(h)
 
 
+def test_kernel_timing_rejects_a_negative_stride():
+    """dgmg_kernel_timing(h, k): k >= 1 times every k-th top-level patch-solve
+    launch, 0 stops; a negative stride is refused before any HIP call."""
+    lib = D.load_library()
+    g = synth.uniform_grid(3, 2, 1.0, False)
+    h, keep = D.setup_handle(g, synth.Method(P=2, smoother="FA"))
+    try:
+        assert lib.dgmg_kernel_timing(h, -1) == -1  # DGMG_EINVAL
+        assert b"negative stride" in lib.dgmg_last_error(h)
+    finally:
+        lib.dgmg_destroy(h)
+
+
 def test_batch_layout_host_side():
     """Batch setup (host only): member workspaces are disjoint, aligned and inside
     the batch workspace; unknown offsets follow the member sizes."""
