@@ -797,7 +797,7 @@ __device__ __forceinline__ void fdm_pass(T* __restrict__ tile, T* __restrict__ t
 }
 
 // The last forward and the first backward contraction of tile dimension 2
-// in one pass (FP64, lines of at most 16): a line block's forward results,
+// in one pass (FP64, lines of 5 to 16): a line block's forward results,
 // scaled by post(line, j, value), stay in registers as the operand of the
 // backward product instead of going through the tile and a barrier.  The f64
 // result layout makes this possible: lane (li, lk) ends the forward product
@@ -817,7 +817,7 @@ __device__ __forceinline__ void fdm_pass_fused2(double* __restrict__ tile, doubl
   constexpr int LINES = NA * ipow(NL, DIM - 2);
   constexpr int STRIDE = fdm_pitch<NA>() * NL;
   constexpr int KS = BOp<T, LEN>::KS, NB = BOp<T, LEN>::NB, MB = (LINES + 15) / 16;
-  static_assert(DIM == 3 && NB == 1 && KS == 4, "lines of 13 to 16 values");
+  static_assert(DIM == 3 && NB == 1 && KS >= 2, "lines of 5 to 16 values");
   static_assert(BOp<T, BLEN>::KS == KS && BOp<T, BLEN>::NB == NB, "operand register shape");
   using M = Mfma<T>;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -851,11 +851,12 @@ __device__ __forceinline__ void fdm_pass_fused2(double* __restrict__ tile, doubl
       v[r] = j < LEN ? sv : T(0);
     }
 #pragma unroll
-    for (int r = 0; r < (TAIL ? 3 : 4); ++r) out = M::op(Bb.b[0][r], v[r], out);
+    for (int r = 0; r < (TAIL ? KS - 1 : KS); ++r) out = M::op(Bb.b[0][r], v[r], out);
     if constexpr (TAIL) {
-      // the last contraction index LEN - 1 = 4 * 3 + 0 is held by lane (li, 0)
-      // in register 3: broadcast it to the line's four lanes, rank-one update
-      const T at = __shfl(v[3], li, 64);
+      // the last contraction index LEN - 1 = 4 (KS - 1) + 0 is held by lane
+      // (li, 0) in register KS - 1: broadcast it to the line's four lanes,
+      // rank-one update
+      const T at = __shfl(v[KS - 1], li, 64);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = imin(M::row(lk, r), LEN - 1);
@@ -1083,8 +1084,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(fdm_mi
                         NL > DGMG_FDM_VALU_MAXLEN && BOp<T, NA>::KS == BOp<T, NL>::KS &&
                         BOp<T, NA>::NB == BOp<T, NL>::NB;
   BOp<T, NA> P, Q;
-  // FP64 with lateral lines of 13 to 16: the dimension-2 passes fused
-  constexpr bool FUSE2 = DGMG_FDM_FUSE2 && PING && sizeof(T) == 8 && NL > 12 && NL <= 16;
+  // FP64 with lateral lines of at most 16: the dimension-2 passes fused
+  constexpr bool FUSE2 = DGMG_FDM_FUSE2 && PING && sizeof(T) == 8 && NL <= 16;
   // FP64 lateral lines with NL = 1 (mod 4): the last row of each of their
   // four matrices in LDS for the rank-one tail of those passes (in FP32 the
   // 16x16x4 product costs half as much and the tail measured slower)
