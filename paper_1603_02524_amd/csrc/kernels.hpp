@@ -631,8 +631,18 @@ template <int NA, int NL, int DIM>
 constexpr int fdm_tile_padded() {
   return fdm_pitch<NA>() * ipow(NL, DIM - 1);
 }
+// Lines up to this length are contracted on the VALU, longer ones on the
+// matrix cores (fdm_pass_any).
+#ifndef DGMG_FDM_VALU_MAXLEN
+#define DGMG_FDM_VALU_MAXLEN 9
+#endif
+// Default block size of a patch solve (the autotuner may choose another): a
+// thread per line of the longest pass, at most 256; 3D tiles whose passes all
+// run on the matrix cores take 4 waves, the size the autotuner picks for them
+// (16 x 13 x 13, 13^3, 11^3 in FP64 and FP32).
 template <int NA, int NL, int DIM>
 constexpr int fdm_threads() {
+  if (DIM == 3 && NA > DGMG_FDM_VALU_MAXLEN && NL > DGMG_FDM_VALU_MAXLEN) return 256;
   return imin(256, round64(imax(ipow(NL, DIM - 1), NA * ipow(NL, DIM - 2))));
 }
 template <class T, int NA, int NL, int DIM>
@@ -936,11 +946,8 @@ __device__ __forceinline__ void fdm_pass_valu(T* __restrict__ tile, const T* __r
 // Contraction pass of tile dimension TD on the unit that suits its length:
 // lines up to DGMG_FDM_VALU_MAXLEN long go to the VALU (the matrix-core form
 // would pad a length-9 line to 12 x 16, 42 % useful work), longer ones to the
-// matrix cores (measured on the box: length 13 lateral passes on the VALU made
+// matrix cores (measured on an MI355X: length 13 lateral passes on the VALU made
 // the 16 x 13 x 13 patch solve 9 % slower, every pass on the VALU 35 %).
-#ifndef DGMG_FDM_VALU_MAXLEN
-#define DGMG_FDM_VALU_MAXLEN 9
-#endif
 template <class T, int NA, int NL, int DIM, int TD, class Post = NoPost>
 __device__ __forceinline__ void fdm_pass_any(T* __restrict__ tile, T* __restrict__ trash, const T* __restrict__ Bm,
                                              const T* __restrict__ BTm, Post post = Post()) {
