@@ -47,7 +47,7 @@ HBM_PEAK_GBPS = 8000.0
 # the patch-solve section of kernels.hpp is compared at run time and the
 # figure dropped on any change.
 TRAFFIC = {"bytes_per_launch": 133.7e6,
-           "kernel_src_sha256": "3e354a65284d67ada171fbe987be52fb81ae7c25263fc056586795f7d219c9b4",
+           "kernel_src_sha256": "21eeba7092ae86177bd0f64650ee51eb25155c3bbcf43ef78c7fe3c4e1f6d4cc",
            "profile": "profiles/fdm_p8_c2_fp64_pmc_traffic.md"}
 KERNEL_SOURCE = "paper_1603_02524_amd/csrc/kernels.hpp"
 KERNEL_SECTION = ("// ================================================================ FDM patch solve",
