@@ -289,7 +289,9 @@ def test_fullsize_mixed_solve_reaches_the_true_residual():
 
 @pytest.mark.parametrize("dim,n,periodic,P", [(3, (12, 11, 10), (False, True, False), 8),
                                               (2, (64, 64), (True, False), 16),
-                                              (3, (17, 16, 16), True, 4)])
+                                              (3, (17, 16, 16), True, 4),
+                                              (3, (8, 8, 8), False, 12),
+                                              (3, (8, 6, 6), (False, False, True), 16)])
 def test_owner_computes_operator_on_large_levels(dim, n, periodic, P):
     """Levels with at least 64k element lines take the one-launch owner-computes
     operator (the parity grids above are smaller and take the two-launch form):
