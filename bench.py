@@ -187,12 +187,12 @@ def _dominant_roofline(S, m, kt, word):
     return roof
 
 
-def _smoothing_step_roofline(S, m, word, reps=20):
-    """One top-level smoothing step (FA: D sweeps, each residual apply + patch solves +
-    overlap summation; EA: one) timed with events on the solver's stream, against its
-    attainable roof max(bytes / HBM peak, flops / compute peak)."""
+def _smoothing_step_roofline(S, m, word, reps=20, level=None):
+    """One smoothing step of the top level (or of `level`) (FA: D sweeps, each residual
+    apply + patch solves + overlap summation; EA: one) timed with events on the solver's
+    stream, against its attainable roof max(bytes / HBM peak, flops / compute peak)."""
     import torch
-    L = S.num_levels - 1
+    L = S.num_levels - 1 if level is None else level
     P, n_o, n = S.level_info(L)
     dim = S.grid.dim
     dt = torch.float64 if m.precision == "fp64" else torch.float32
@@ -213,8 +213,9 @@ def _smoothing_step_roofline(S, m, word, reps=20):
     byts = sweeps * 3.0 * word * n
     peak = FP64_VALU_PEAK_TFLOPS if m.precision == "fp64" else FP32_MFMA_PEAK_TFLOPS
     t_roof = max(byts / (HBM_PEAK_GBPS * 1e9), flops / (peak * 1e12)) * 1e3
-    return {"ms": ms, "roof_ms": t_roof, "frac": t_roof / ms, "flops": flops, "alg_bytes": byts,
-            "sweeps": sweeps, "bound": "hbm" if byts / (HBM_PEAK_GBPS * 1e9) > flops / (peak * 1e12) else "compute"}
+    return {"level": L, "P": P, "n_dof": n, "ms": ms, "roof_ms": t_roof, "frac": t_roof / ms, "flops": flops,
+            "alg_bytes": byts, "sweeps": sweeps,
+            "bound": "hbm" if byts / (HBM_PEAK_GBPS * 1e9) > flops / (peak * 1e12) else "compute"}
 
 
 def _cpu_model():
@@ -524,6 +525,8 @@ def main():
         raise SystemExit(1)
     roof = _dominant_roofline(S, m, kt, 8)
     step = _smoothing_step_roofline(S, m, 8)
+    # every smoothed level's step against its own roof (where the V-cycle's time goes)
+    steps_by_level = [_smoothing_step_roofline(S, m, 8, level=l) for l in range(S.num_levels - 1, 0, -1)]
 
     out = {"metric": METRIC, "value": n / sec, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
@@ -534,7 +537,7 @@ def main():
                       "precision": m.precision, "tol": w.tol, "seed": w.seed,
                       "iterations": st["iterations"], "true_rel_residual": true_rel,
                       "autotuned_waves": {f"l{l}k{k}": v[0] for (l, k), v in sorted(tuning.items())}},
-           "roofline": roof, "smoothing_step": step}
+           "roofline": roof, "smoothing_step": step, "smoothing_steps_by_level": steps_by_level}
 
     _log("timing mixed-precision solves")
     wm = synth.with_method(w, precision="mixed")
